@@ -1,0 +1,252 @@
+"""FP64 CPU oracle for the Shan-Chen D3Q19 lattice Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_1904_11792_amd``) and never imports it.
+
+The arithmetic lives in ``sc_oracle.c`` (plain C, FP64, OpenMP over z); this
+module is a ctypes wrapper plus the slow drivers built on it:
+
+* ``step`` / ``run``          -- Eq. (3) with the velocity shift of Eq. (6)
+                                 (Section 2 of the paper)
+* ``fields``                  -- rho, j (Eq. 4), F (Eq. 5), physical velocity
+* ``init_ligament``           -- the perturbed cylinder of Section 3 (Fig. 1)
+* ``diag``                    -- mass, momentum, rho range, neck density
+* ``coexistence``             -- flat-interface run to steady state
+* ``label``                   -- 6-connected droplet labelling
+
+Arrays are numpy float64 with shape (19, nz, ny, nx), C-contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sc_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+Q = 19
+
+
+def build() -> str:
+    """Compile sc_oracle.c with gcc into oracle/liboracle.so (always rebuilds)."""
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-shared", "-fPIC",
+           _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    """Load the oracle library, compiling it first if it has never been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    L = ctypes.CDLL(_SO)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    ci, cd, cl, cu64 = ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_uint64
+    L.orc_lattice.argtypes = [ip, ip, ip, dp]
+    L.orc_lattice.restype = None
+    L.orc_psi.argtypes = [cd, cd]
+    L.orc_psi.restype = cd
+    L.orc_pressure.argtypes = [cd, cd, cd]
+    L.orc_pressure.restype = cd
+    L.orc_feq.argtypes = [cd, cd, cd, cd, dp]
+    L.orc_feq.restype = None
+    L.orc_step.argtypes = [ci, ci, ci, cd, cd, cd, dp, dp]
+    L.orc_step.restype = ci
+    L.orc_run.argtypes = [ci, ci, ci, cd, cd, cd, cl, dp, dp]
+    L.orc_run.restype = ci
+    L.orc_fields.argtypes = [ci, ci, ci, cd, cd, dp, dp, dp, dp, dp]
+    L.orc_fields.restype = ci
+    L.orc_splitmix64.argtypes = [cu64]
+    L.orc_splitmix64.restype = cu64
+    L.orc_uniform.argtypes = [cu64, cu64]
+    L.orc_uniform.restype = cd
+    L.orc_init_ligament.argtypes = [ci, ci, ci, ci, cd, cd, cd, cd, cd, cd, cd, cd, cd,
+                                     cu64, dp]
+    L.orc_init_ligament.restype = ci
+    L.orc_diag.argtypes = [ci, ci, ci, ci, dp, dp]
+    L.orc_diag.restype = ci
+    L.orc_label.argtypes = [ci, ci, ci, dp, cd, i32p]
+    L.orc_label.restype = cl
+    _lib = L
+    return L
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _shape(f: np.ndarray):
+    if f.ndim != 4 or f.shape[0] != Q:
+        raise ValueError("populations must have shape (19, nz, ny, nx)")
+    _, nz, ny, nx = f.shape
+    return nx, ny, nz
+
+
+def lattice():
+    """(cx, cy, cz, w) of the D3Q19 set in the oracle's direction order."""
+    L = lib()
+    cx = (ctypes.c_int * Q)()
+    cy = (ctypes.c_int * Q)()
+    cz = (ctypes.c_int * Q)()
+    w = (ctypes.c_double * Q)()
+    L.orc_lattice(cx, cy, cz, w)
+    return (np.array(cx[:]), np.array(cy[:]), np.array(cz[:]), np.array(w[:]))
+
+
+def psi(rho: float, rho0: float = 1.0) -> float:
+    return lib().orc_psi(float(rho), float(rho0))
+
+
+def pressure(rho: float, G: float, rho0: float = 1.0) -> float:
+    """Eq. (7) of the paper."""
+    return lib().orc_pressure(float(rho), float(G), float(rho0))
+
+
+def feq(rho: float, u) -> np.ndarray:
+    out = np.zeros(Q)
+    lib().orc_feq(float(rho), float(u[0]), float(u[1]), float(u[2]), _dp(out))
+    return out
+
+
+def step(f: np.ndarray, tau: float, G: float, rho0: float = 1.0) -> np.ndarray:
+    """One update; returns a new array."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nx, ny, nz = _shape(f)
+    out = np.empty_like(f)
+    if lib().orc_step(nx, ny, nz, tau, G, rho0, _dp(f), _dp(out)) != 0:
+        raise MemoryError("oracle step failed")
+    return out
+
+
+def run(f: np.ndarray, nsteps: int, tau: float, G: float, rho0: float = 1.0) -> np.ndarray:
+    """nsteps updates; returns a new array (the input is left untouched)."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    nx, ny, nz = _shape(f)
+    scratch = np.empty_like(f)
+    if lib().orc_run(nx, ny, nz, tau, G, rho0, int(nsteps), _dp(f), _dp(scratch)) != 0:
+        raise MemoryError("oracle run failed")
+    return f
+
+
+def fields(f: np.ndarray, G: float, rho0: float = 1.0) -> dict:
+    """rho (nz,ny,nx); j, F, u (3,nz,ny,nx); u is the physical (j + F/2)/rho."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nx, ny, nz = _shape(f)
+    rho = np.empty((nz, ny, nx))
+    j = np.empty((3, nz, ny, nx))
+    F = np.empty((3, nz, ny, nx))
+    u = np.empty((3, nz, ny, nx))
+    if lib().orc_fields(nx, ny, nz, G, rho0, _dp(f), _dp(rho), _dp(j), _dp(F), _dp(u)) != 0:
+        raise MemoryError("oracle fields failed")
+    return {"rho": rho, "j": j, "F": F, "u": u}
+
+
+def splitmix64(s: int) -> int:
+    return int(lib().orc_splitmix64(ctypes.c_uint64(s & (2**64 - 1))))
+
+
+def uniform(seed: int, index: int) -> float:
+    return float(lib().orc_uniform(seed & (2**64 - 1), index & (2**64 - 1)))
+
+
+def init_ligament(nx: int, ny: int, nz: int, *, axis: int = 2, R0: float,
+                  amp_rel: float, wavelength: float, c1: float | None = None,
+                  c2: float | None = None, width: float = 2.0, rho_l: float,
+                  rho_v: float, noise_amp: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Perturbed liquid cylinder at rest (Section 3); see sc_oracle.c."""
+    plane = [(ny, nz), (nx, nz), (nx, ny)][axis]
+    c1 = plane[0] / 2.0 if c1 is None else c1
+    c2 = plane[1] / 2.0 if c2 is None else c2
+    f = np.empty((Q, nz, ny, nx))
+    rc = lib().orc_init_ligament(nx, ny, nz, axis, R0, amp_rel, wavelength, c1, c2, width,
+                                 rho_l, rho_v, noise_amp, seed & (2**64 - 1), _dp(f))
+    if rc != 0:
+        raise ValueError("bad ligament spec")
+    return f
+
+
+def diag(f: np.ndarray, axis: int = 2) -> dict:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nx, ny, nz = _shape(f)
+    out = np.zeros(8)
+    if lib().orc_diag(nx, ny, nz, axis, _dp(f), _dp(out)) != 0:
+        raise MemoryError("oracle diag failed")
+    return {"mass": out[0], "mom": out[1:4].copy(), "rho_min": out[4], "rho_max": out[5],
+            "neck_rho": out[6], "nonfinite": int(out[7])}
+
+
+def label(rho: np.ndarray, thresh: float):
+    """6-connected periodic components of rho > thresh: (count, labels int32)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    nz, ny, nx = rho.shape
+    lab = np.zeros(rho.shape, dtype=np.int32)
+    cnt = lib().orc_label(nx, ny, nz, _dp(rho), thresh,
+                          lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if cnt < 0:
+        raise MemoryError("oracle label failed")
+    return int(cnt), lab
+
+
+@dataclass
+class Coexistence:
+    rho_l: float
+    rho_v: float
+    steps: int
+    residual: float
+    converged: bool
+
+
+def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
+                tol: float = 1e-12, chunk: int = 1000, max_steps: int = 200_000,
+                rho_hi: float = 2.1, rho_lo: float = 0.1, width: float = 4.0) -> Coexistence:
+    """Coexisting densities from a flat interface on a 1 x 1 x n periodic slab.
+
+    Start: rho = lo + (hi - lo)/2 [tanh(2(z - z1)/W) - tanh(2(z - z2)/W)] with
+    z1 = n/4 - 1/2 and z2 = 3n/4 - 1/2 (liquid on [n/4, 3n/4)), populations at
+    rest equilibrium.  The run proceeds in chunks; the residual of a chunk is
+    the largest density change over it.  It stops when the residual is below
+    ``tol``, when it has grown 100-fold above the smallest residual seen once
+    that one is below 1e-8 (the quasi-1D slab at tau = 1 develops a slowly
+    growing counter-flow drift seeded by round-off), or at ``max_steps``.  The state with the smallest
+    residual is reported: liquid density at z = n/2, vapour at z = 0.
+    The velocity-shift forcing makes these depend on tau as well as on G.
+    """
+    z = np.arange(n, dtype=np.float64)
+    z1, z2 = n / 4 - 0.5, 3 * n / 4 - 0.5
+    rho = rho_lo + (rho_hi - rho_lo) * 0.5 * (np.tanh(2.0 * (z - z1) / width)
+                                             - np.tanh(2.0 * (z - z2) / width))
+    _, _, _, w = lattice()
+    f = np.empty((Q, n, 1, 1))
+    for a in range(Q):
+        f[a, :, 0, 0] = w[a] * rho
+    prev = rho.copy()
+    best = (np.inf, 0, float(rho[n // 2]), float(rho[0]))
+    steps = 0
+    while steps < max_steps:
+        f = run(f, chunk, tau, G, rho0)
+        steps += chunk
+        cur = f.sum(axis=0)[:, 0, 0]
+        if not np.all(np.isfinite(cur)):
+            break
+        res = float(np.max(np.abs(cur - prev)))
+        prev = cur
+        if res < best[0]:
+            best = (res, steps, float(cur[n // 2]), float(cur[0]))
+        if res < tol or (best[0] < 1e-8 and res > 100.0 * best[0]):
+            break
+    return Coexistence(best[2], best[3], best[1], best[0], best[0] < tol)
