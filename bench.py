@@ -1,0 +1,201 @@
+"""Throughput of the fused Shan-Chen D3Q19 step on one MI355X.
+
+Default workload: the large single ligament, 256 x 256 x 1024 nodes, FP32
+storage and arithmetic, tau 0.8, G -5.5, R0 24, five waves along z,
+amplitude 0.05 R0, density noise +-1e-4 (seed 1); liquid/vapour densities
+from the library's FP64 flat-interface coexistence run on the GPU.  Inputs
+are synthetic and resident in HBM before timing starts.
+
+One step = one launch of the fused psi/force/collide/stream kernel over the
+whole grid.  Prints one JSON line (metric MLUPS) with a roofline object for
+that kernel (algorithmic bytes 19 loads + 19 stores per node, timed with
+HIP events on the kernel's own stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--storage f32|f64|f16s|bf16s]
+                  [--form single|batch] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1904_11792_amd", "csrc", f)
+                  for f in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h")]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = t.get(storage)
+    if not e or e.get("kernel_digest") != kernel_digest() or e.get("nodes") != nodes:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, rho_l, rho_v, budget_s=12.0):
+    """The FP64 oracle on a z-slab of the same ligament (bounded sample)."""
+    import oracle
+
+    nz_s = 64
+    f = oracle.init_ligament(spec.nx, spec.ny, nz_s, R0=spec.R0, amp_rel=spec.amp_rel,
+                             wavelength=spec.wavelength, rho_l=rho_l, rho_v=rho_v,
+                             noise_amp=spec.noise_amp, seed=spec.seed)
+    t0 = time.perf_counter()
+    f = oracle.run(f, 1, spec.tau, spec.G)  # calibration step (also pages the arrays in)
+    t1 = time.perf_counter() - t0
+    steps = max(2, min(50, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    f = oracle.run(f, steps, spec.tau, spec.G)
+    el = time.perf_counter() - t0
+    nodes = spec.nx * spec.ny * nz_s
+    return {"value": round(nodes * steps / el / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} steps on a {spec.nx}x{spec.ny}x{nz_s} periodic z-slab "
+                      f"of the same ligament ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
+    ap.add_argument("--form", default="single", choices=["single", "batch"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-chunk", type=int, default=0)
+    ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU z-slab "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_1904_11792_amd import lbm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    if args.form == "batch":
+        return bench_batch(args, lbm, workloads, stream)
+
+    spec = workloads.LARGE_FP32
+    print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
+    rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+    lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=args.storage,
+                      rho_ref=rho_v, stream=stream)
+    lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength,
+                      rho_l=rho_l, rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
+    if args.launch:
+        lat.set_launch(*[int(v) for v in args.launch.split(",")])
+    if args.graph_chunk:
+        lat.set_graph_chunk(args.graph_chunk)
+    launch = lat.get_launch()
+
+    # plain copy kernel of the same size as one lattice pass: practical HBM ceiling
+    nbytes = 19 * spec.n * BYTES_PER_POP[args.storage]
+    with torch.cuda.stream(stream):
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        lbm.lbm_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    e0.record(stream)
+    for _ in range(10):
+        lbm.lbm_device_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    e1.record(stream)
+    e1.synchronize()
+    copy_gbs = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    mlups = spec.n * args.steps / (ms * 1e-3) / 1e6
+    d = lat.diagnostics()
+    alg_bytes = 2 * 19 * BYTES_PER_POP[args.storage] * spec.n
+    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage, spec.n)
+    out = {
+        "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": spec.name + f" R0=24 tau=0.8 G=-5.5 storage={args.storage}",
+                   "grid": [spec.nx, spec.ny, spec.nz], "launch": list(launch),
+                   "graph_chunk": args.graph_chunk},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "copy_kernel_GBps": round(copy_gbs, 1),
+        "state_check": {"mass": d["mass"], "nonfinite": d["nonfinite"], "step": d["step"]},
+    }
+    print(f"# {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, rho_l, rho_v)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, lbm, workloads, stream):
+    import torch
+
+    cases = workloads.batch64()
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage=args.storage) for c in cases]
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel,
+                               wavelength=c.wavelength, seed=c.seed) for c in cases]
+    b = lbm.Batch(params, stream=stream)
+    b.init(specs)
+    b.set_graph_chunk(args.graph_chunk or 100)
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    diags = b.diagnostics()
+    live = [c for c, d in zip(cases, diags) if d["nonfinite"] == 0]
+    nodes = sum(c.n for c in live)
+    mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+    out = {"metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.storage, "data": "synthetic",
+           "config": {"workload": f"batch64: {len(cases)} ligaments, {sum(c.n for c in cases)} nodes",
+                      "live_cases": len(live), "frozen_cases": len(cases) - len(live)}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

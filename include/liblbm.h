@@ -1,0 +1,277 @@
+/*
+ * liblbm -- single-relaxation-time Shan-Chen D3Q19 lattice Boltzmann on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Chiappini, Xue, Falcucci & Sbragaglia, "Ligament
+ * break-up simulation through pseudo-potential Lattice Boltzmann Method",
+ * Section 2: D3Q19 populations on a periodic Cartesian grid, BGK relaxation
+ * with one time tau (Eqs. 1 and 3), the second-order equilibrium (Eq. 2,
+ * with its leading 1), moments (Eq. 4), the single-belt pseudo-potential
+ * force (Eq. 5) with psi = rho0 (1 - exp(-rho/rho0)), entering through the
+ * velocity shift u' = u + tau F / rho of Eq. (6).  Lattice units: dt = dx = 1,
+ * c_s^2 = 1/3.  The extra forcing term F_a of Eq. (3) is zero: the
+ * interaction acts only through the shift.
+ *
+ * Conventions shared by every call
+ *   - Grid nx * ny * nz, periodic in all three directions, each extent >= 1.
+ *     Node index ((z * ny) + y) * nx + x, x fastest.
+ *   - Canonical population order (used by every FP64 export/import):
+ *       0 rest; 1..6 = +x, -x, +y, -y, +z, -z;
+ *       7..18 = +x+y, -x-y, +x-y, -x+y, +x+z, -x-z, +x-z, -x+z,
+ *               +y+z, -y-z, +y-z, -y+z   (opposite directions adjacent).
+ *     A population array is [19][n] doubles, population-major.
+ *     "State at step t" means f_a(x, t): post-streaming, before collision.
+ *   - G is signed; phase separation needs G < 0 (the paper's G0 = 5.3 of
+ *     Section 4 is G = -5.3 here).
+ *   - Every call returns an lbm_status (0 = LBM_OK).  No call throws or
+ *     aborts.  On error the thread-local message lbm_last_error() says why,
+ *     and state is left as it was, except after LBM_ERR_DEVICE, which
+ *     poisons the context (later calls on it return LBM_ERR_STATE).
+ *   - Device memory is owned by the caller: the library allocates none for
+ *     the lattice, only borrows the workspace given to lbm_create.
+ *   - Work is ordered on the HIP stream given at creation.  Only calls that
+ *     return host data synchronise that stream (lbm_diagnostics,
+ *     lbm_read_diag_history, lbm_get_fields with on_device = 0,
+ *     lbm_coexistence, lbm_autotune).
+ */
+#ifndef LIBLBM_H
+#define LIBLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID_ARG = -1,    /* bad argument; nothing changed */
+    LBM_ERR_UNSUPPORTED = -2,    /* valid request this build does not provide */
+    LBM_ERR_DEVICE = -3,         /* a HIP call failed; the context is poisoned */
+    LBM_ERR_STATE = -4,          /* call on a poisoned or uninitialised object */
+    LBM_ERR_DIVERGED = -5,       /* non-finite or non-positive density found */
+    LBM_ERR_BUFFER_TOO_SMALL = -6
+} lbm_status;
+
+/* Pseudo-potential form (Section 2, below Eq. 5): psi = rho0 (1 - exp(-rho/rho0)). */
+typedef enum { LBM_PSI_EXP = 0 } lbm_psi;
+
+/*
+ * Population storage.  F64 and F32 store f_a as is and compute in the same
+ * precision.  F16S and BF16S store the shifted value f_a - w_a rho_ref in
+ * IEEE half / bfloat16 (round-to-nearest-even both ways) and compute in FP32.
+ */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
+
+typedef struct {
+    int32_t nx, ny, nz; /* grid extents, each >= 1, n = nx*ny*nz <= 2^31 / 19 */
+    double tau;         /* relaxation time, > 0.5 (Eq. 1) */
+    double G;           /* interaction strength of Eq. (5), signed, finite */
+    int32_t psi;        /* lbm_psi */
+    double rho0;        /* reference density of psi, > 0 (the paper uses 1) */
+    int32_t storage;    /* lbm_storage */
+    double rho_ref;     /* shift density for F16S/BF16S (ignored otherwise) */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/*
+ * Bytes of device workspace a context with these parameters needs (two
+ * lattices of 19 populations plus diagnostic buffers), or 0 if the
+ * parameters are invalid.
+ */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/*
+ * Create a context.  d_workspace: device pointer, 256-byte aligned, at least
+ * lbm_workspace_bytes(p) bytes, owned by the caller and borrowed until
+ * lbm_destroy.  hip_stream: a hipStream_t (NULL = the null stream).  The
+ * lattice content is undefined until lbm_init_ligament or
+ * lbm_set_populations.  Errors: INVALID_ARG (bad params, null pointers,
+ * misalignment), BUFFER_TOO_SMALL, DEVICE.
+ */
+int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
+               lbm_ctx **out);
+
+/* Release host-side state and captured graphs.  Never frees the workspace. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/*
+ * Coexisting liquid/vapour densities for (G, tau, psi, rho0), in FP64 on the
+ * current HIP device: a flat interface on a 1 x 1 x 128 periodic slab
+ * (liquid on [32, 96), tanh start of width 4 between densities 2.1 rho0 and
+ * 0.1 rho0, at rest) is advanced in chunks of 1000 steps of the same update
+ * (Eqs. 2-6) until the largest density change over a chunk is below 1e-12,
+ * until that change has grown 100-fold above its smallest value once the
+ * smallest is below 1e-8, or for 200 chunks; the densities at z = 64
+ * (liquid) and z = 0 (vapour) of the chunk with the smallest change are
+ * returned.  With the velocity-shift forcing they depend on tau as well as
+ * G.  Synchronous.  Errors: INVALID_ARG (G >= -4 has no coexistence for
+ * psi_exp with rho0 = 1, tau <= 0.5, null outputs), DIVERGED, DEVICE.
+ */
+int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l,
+                    double *rho_v);
+
+/*
+ * Ligament initial condition (Section 3, Fig. 1): a liquid cylinder along
+ * `axis` whose radius is modulated by a cosine with an integer number of
+ * waves over the period (the paper's sine of 4x/L is not periodic on the
+ * domain; its amplitude R0/10 is amp_rel = 0.1):
+ *   R(s) = R0 (1 + amp_rel cos(2 pi s / wavelength)), s the axis coordinate,
+ *   rho  = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh(2 (r - R(s)) / width),
+ *   rho += noise_amp (2U - 1), U = top 53 bits of SplitMix64(seed + node)
+ *          / 2^53 (Steele, Lea & Flood 2014; counter-based),
+ *   f_a  = w_a rho (equilibrium at rest),
+ * r = distance from (c1, c2), the axis position in the cross-section (c1
+ * along the lower-numbered in-plane axis).  rho_l <= 0 or rho_v <= 0 means
+ * "use lbm_coexistence(G, tau)".  Resets the step counter to 0.
+ */
+typedef struct {
+    int32_t axis;                  /* 0 = x, 1 = y, 2 = z */
+    double R0, amp_rel, wavelength; /* R0 > 0, wavelength > 0 */
+    double c1, c2;                 /* axis position in node units */
+    double width;                  /* tanh width, > 0 */
+    double rho_l, rho_v;           /* densities; <= 0 selects coexistence */
+    double noise_amp;              /* >= 0 */
+    uint64_t seed;
+} lbm_ligament;
+
+int lbm_init_ligament(lbm_ctx *ctx, const lbm_ligament *spec);
+
+/*
+ * Advance nsteps >= 0 time steps of Eq. (3) with the force of Eq. (5) and
+ * the shift of Eq. (6), fused into one kernel per step (psi recomputed for a
+ * one-node halo in on-chip memory; pull streaming between two lattices).
+ * Asynchronous and stream-ordered; divergence is reported by
+ * lbm_diagnostics, not here.
+ */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/*
+ * Export fields of the current state as FP64.  mask: LBM_FIELD_* bits.
+ *   rho   [n]      density (Eq. 4)
+ *   u     [3][n]   physical velocity (sum_a c_a f_a + F/2) / rho
+ *   force [3][n]   Shan-Chen force (Eq. 5)
+ *   pop   [19][n]  populations f_a(x, t) in canonical order
+ * Pointers of unrequested fields may be NULL.  on_device = 1: the pointers
+ * are device pointers (stream-ordered, no sync); 0: host pointers (syncs).
+ */
+enum { LBM_FIELD_RHO = 1, LBM_FIELD_U = 2, LBM_FIELD_FORCE = 4, LBM_FIELD_POP = 8 };
+int lbm_get_fields(lbm_ctx *ctx, uint32_t mask, double *rho, double *u, double *force,
+                   double *pop, int32_t on_device);
+
+/* Replace the state by pop[19][n] (canonical FP64, f_a(x, t)); step counter kept. */
+int lbm_set_populations(lbm_ctx *ctx, const double *pop, int32_t on_device);
+
+/*
+ * Global diagnostics of the current state, reduced in FP64 on the device
+ * (wavefront shuffles, per-block partials, fixed-order final pass, so the
+ * result is reproducible):
+ *   mass = sum rho, mom = sum_x sum_a c_a f_a (equal to the physical total
+ *   since the periodic force sums to zero), rho_min, rho_max,
+ *   neck_rho = min over the axis coordinate of the max of rho over the
+ *   cross-section (axis set by lbm_set_axis, default z),
+ *   nonfinite = number of nodes with a non-finite population or rho <= 0.
+ * Synchronises.  Returns LBM_ERR_DIVERGED (with *out filled) if nonfinite > 0.
+ */
+typedef struct {
+    int64_t step;
+    double mass, mom[3], rho_min, rho_max, neck_rho;
+    int64_t nonfinite;
+} lbm_diag;
+
+int lbm_diagnostics(lbm_ctx *ctx, lbm_diag *out);
+
+/* Axis along which neck_rho is taken (0 = x, 1 = y, 2 = z). */
+int lbm_set_axis(lbm_ctx *ctx, int32_t axis);
+
+/*
+ * Asynchronous diagnostics: enqueue the same reduction into a device ring of
+ * LBM_DIAG_RING records without synchronising (for break-up detection over
+ * long runs).  lbm_read_diag_history copies the records enqueued since the
+ * last read (oldest first; at most LBM_DIAG_RING, older ones are
+ * overwritten) and synchronises.  *count receives the number copied.
+ */
+enum { LBM_DIAG_RING = 4096 };
+int lbm_record_diag(lbm_ctx *ctx);
+int lbm_read_diag_history(lbm_ctx *ctx, lbm_diag *out, int32_t max, int32_t *count);
+
+/* Steps taken since the last lbm_init_ligament. */
+int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
+
+/*
+ * Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
+ * nodes (one thread each) marching zchunk planes along z.  Supported tiles:
+ * see lbm_list_tiles.  zchunk >= 1.
+ */
+typedef struct {
+    int32_t tile_x, tile_y, zchunk;
+} lbm_launch;
+
+int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *l);
+int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *l);
+/* Copy up to max supported tiles into out; *count receives the total. */
+int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count);
+
+/*
+ * Autotuner: time each supported tile shape and z-chunk on this context's
+ * grid (steps_per_candidate launches from the current lattice into the
+ * spare one, so the state is unchanged), pick the fastest, set it, and store
+ * it in the JSON cache named by the environment variable LBM_TUNE_CACHE (if
+ * set) keyed by device architecture, storage and grid.  A later lbm_create
+ * with the same key takes the cached shape.  Synchronous.
+ */
+int lbm_autotune(lbm_ctx *ctx, int32_t steps_per_candidate, lbm_launch *best,
+                 double *best_mlups);
+
+/*
+ * hipGraph capture of the step loop: lbm_step runs whole chunks of
+ * `chunk_steps` (even, 0 disables) as one captured graph each.  Needs a
+ * non-null stream.  Captured graphs are rebuilt when the launch shape
+ * changes and released by lbm_destroy.
+ */
+int lbm_set_graph_chunk(lbm_ctx *ctx, int32_t chunk_steps);
+
+/* Thread-local message of the last failing call on this thread (static lifetime). */
+const char *lbm_last_error(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+/*
+ * Calibration: copy `bytes` (multiple of 16) from src to dst (device
+ * pointers) with a plain streaming kernel on `hip_stream`; the HBM ceiling a
+ * bandwidth-bound kernel is compared with.
+ */
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent ligaments of different grids and
+ * parameters advanced by ONE kernel launch per step (a flat list of
+ * (case, tile) work items), optionally replayed as a captured hipGraph.
+ * All cases share one storage kind.  A case whose diagnostics find a
+ * non-finite or non-positive density is frozen: later steps skip it and its
+ * state keeps the values of the step at which it was found.
+ */
+typedef struct lbm_batch lbm_batch;
+
+size_t lbm_batch_workspace_bytes(int32_t ncases, const lbm_params *p);
+int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, size_t ws_bytes,
+                     void *hip_stream, lbm_batch **out);
+int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs);
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+/* Per-case diagnostics (synchronises); frozen cases report nonfinite > 0. */
+int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out);
+/* Per-case FP64 export, as lbm_get_fields, for case `index`. */
+int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho, double *u,
+                         double *force, double *pop, int32_t on_device);
+int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
+int lbm_batch_set_graph_chunk(lbm_batch *b, int32_t chunk_steps);
+int lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBLBM_H */

@@ -56,6 +56,8 @@ def lib():
     ip = ctypes.POINTER(ctypes.c_int)
     i32p = ctypes.POINTER(ctypes.c_int32)
     ci, cd, cl, cu64 = ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_uint64
+    L.orc_num_threads.argtypes = []
+    L.orc_num_threads.restype = ci
     L.orc_lattice.argtypes = [ip, ip, ip, dp]
     L.orc_lattice.restype = None
     L.orc_psi.argtypes = [cd, cd]
@@ -95,6 +97,11 @@ def _shape(f: np.ndarray):
         raise ValueError("populations must have shape (19, nz, ny, nx)")
     _, nz, ny, nx = f.shape
     return nx, ny, nz
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle runs on."""
+    return int(lib().orc_num_threads())
 
 
 def lattice():

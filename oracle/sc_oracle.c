@@ -34,6 +34,9 @@
  *   - Periodic boundaries in x, y and z.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -64,6 +67,16 @@ static int wrap(int i, int n)
 static size_t node(int x, int y, int z, int nx, int ny)
 {
     return ((size_t)z * (size_t)ny + (size_t)y) * (size_t)nx + (size_t)x;
+}
+
+/* Number of OpenMP threads the oracle's loops use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_lattice(int *cx, int *cy, int *cz, double *w)

@@ -1,0 +1,1141 @@
+// Host runtime of liblbm: the C ABI declared in include/liblbm.h.
+//
+// A context borrows one caller-owned device workspace, carved as
+//   [lattice 0][lattice 1][diag partials][slice maxima][latest record][ring]
+// and orders all work on the caller's HIP stream.  Nothing here allocates
+// device memory on the step path.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/liblbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage) {
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        default: return 2;
+    }
+}
+
+int validate_params(const lbm_params *p) {
+    if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    const int64_t n = int64_t(p->nx) * p->ny * p->nz;
+    if (n > int64_t(0x7fffffff))
+        return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1", (long long)n);
+    if (!(p->tau > 0.5) || !isfinite(p->tau))
+        return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 0.5 (got %g)", p->tau);
+    if (!isfinite(p->G)) return fail(LBM_ERR_INVALID_ARG, "G must be finite");
+    if (p->psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", p->psi);
+    if (!(p->rho0 > 0.0) || !isfinite(p->rho0))
+        return fail(LBM_ERR_INVALID_ARG, "rho0 must be finite and > 0");
+    if (p->storage < LBM_F64 || p->storage > LBM_BF16S)
+        return fail(LBM_ERR_INVALID_ARG, "unknown storage kind %d", p->storage);
+    if (!isfinite(p->rho_ref)) return fail(LBM_ERR_INVALID_ARG, "rho_ref must be finite");
+    return LBM_OK;
+}
+
+struct Layout {
+    int64_t S;
+    size_t lat_bytes, off_lat1, off_part, off_slices, off_latest, off_ring, total;
+    int nparts, nslices;
+};
+
+Layout layout_of(const lbm_params *p) {
+    Layout L;
+    const int64_t n = int64_t(p->nx) * p->ny * p->nz;
+    L.S = (n + 63) / 64 * 64;
+    L.lat_bytes = align_up(size_t(Q) * L.S * elem_bytes(p->storage), 256);
+    L.off_lat1 = L.lat_bytes;
+    L.nparts = diag_blocks(p->nx, p->ny, p->nz);
+    L.nslices = p->nx > p->ny ? (p->nx > p->nz ? p->nx : p->nz) : (p->ny > p->nz ? p->ny : p->nz);
+    L.off_part = 2 * L.lat_bytes;
+    L.off_slices = L.off_part + align_up(sizeof(DiagPartial) * L.nparts, 256);
+    L.off_latest = L.off_slices + align_up(sizeof(unsigned long long) * L.nslices, 256);
+    L.off_ring = L.off_latest + align_up(sizeof(DiagRecord), 256);
+    L.total = L.off_ring + align_up(sizeof(DiagRecord) * LBM_DIAG_RING, 256);
+    return L;
+}
+
+bool is_shifted(int st) { return st == LBM_F16S || st == LBM_BF16S; }
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// ---- tiny JSON cache of tuned launch shapes: {"key": [tx, ty, zchunk], ...}
+std::string tune_key(const lbm_params *p) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s:%d:%dx%dx%d", arch_name().c_str(), p->storage, p->nx, p->ny, p->nz);
+    return buf;
+}
+
+bool cache_lookup(const std::string &key, lbm_launch *out) {
+    const char *path = getenv("LBM_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+    fclose(f);
+    const std::string pat = "\"" + key + "\"";
+    const size_t at = s.find(pat);
+    if (at == std::string::npos) return false;
+    int tx, ty, zc;
+    if (sscanf(s.c_str() + at + pat.size(), " : [%d , %d , %d]", &tx, &ty, &zc) != 3) return false;
+    out->tile_x = tx;
+    out->tile_y = ty;
+    out->zchunk = zc;
+    return true;
+}
+
+void cache_store(const std::string &key, const lbm_launch &l) {
+    const char *path = getenv("LBM_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::vector<std::pair<std::string, lbm_launch>> entries;
+    if (FILE *f = fopen(path, "r")) {
+        std::string s;
+        char buf[4096];
+        size_t k;
+        while ((k = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+        fclose(f);
+        size_t pos = 0;
+        while ((pos = s.find('"', pos)) != std::string::npos) {
+            const size_t end = s.find('"', pos + 1);
+            if (end == std::string::npos) break;
+            std::string k2 = s.substr(pos + 1, end - pos - 1);
+            lbm_launch e;
+            if (sscanf(s.c_str() + end + 1, " : [%d , %d , %d]", &e.tile_x, &e.tile_y, &e.zchunk) == 3 &&
+                k2 != key)
+                entries.emplace_back(k2, e);
+            pos = end + 1;
+        }
+    }
+    entries.emplace_back(key, l);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < entries.size(); ++i)
+        fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", entries[i].first.c_str(), entries[i].second.tile_x,
+                entries[i].second.tile_y, entries[i].second.zchunk, i + 1 < entries.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+// Default launch shape: widest tile that does not overhang x by more than
+// half, and enough z chunks for a few thousand workgroups.
+lbm_launch default_launch(const lbm_params *p) {
+    lbm_launch l;
+    l.tile_x = p->nx >= 64 ? 64 : 32;
+    l.tile_y = 8;
+    const int64_t tiles = int64_t((p->nx + l.tile_x - 1) / l.tile_x) * ((p->ny + l.tile_y - 1) / l.tile_y);
+    int64_t chunks = (2048 + tiles - 1) / tiles;
+    int64_t zc = (p->nz + chunks - 1) / chunks;
+    if (zc < 4) zc = 4;
+    if (zc > p->nz) zc = p->nz;
+    l.zchunk = int(zc);
+    return l;
+}
+
+int check_launch(const lbm_launch *l, int nz) {
+    if (!l) return fail(LBM_ERR_INVALID_ARG, "launch is NULL");
+    if (find_tile(l->tile_x, l->tile_y) < 0)
+        return fail(LBM_ERR_UNSUPPORTED, "tile %dx%d is not compiled in", l->tile_x, l->tile_y);
+    if (l->zchunk < 1) return fail(LBM_ERR_INVALID_ARG, "zchunk must be >= 1");
+    (void)nz;
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Layout lay;
+    void *lat[2];
+    int cur;
+    int axis;
+    int64_t step;
+    bool initialized;
+    bool poisoned;
+    lbm_launch launch;
+    int tile_index;
+    DiagPartial *partials;
+    unsigned long long *slices;
+    DiagRecord *latest;
+    DiagRecord *ring;
+    int64_t ring_written, ring_read;
+    int graph_chunk;
+    hipGraphExec_t gexec;
+    lbm_launch graph_launch;
+};
+
+namespace {
+
+int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
+    if (c) c->poisoned = true;
+    return fail(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_ctx(const lbm_ctx *c) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "context is NULL");
+    if (c->poisoned) return fail(LBM_ERR_STATE, "context is poisoned by an earlier device error");
+    return LBM_OK;
+}
+
+LatticeRef lattice_ref(const lbm_ctx *c, int which) {
+    LatticeRef L;
+    L.lat = c->lat[which];
+    L.nx = c->p.nx;
+    L.ny = c->p.ny;
+    L.nz = c->p.nz;
+    L.storage = c->p.storage;
+    L.pop_stride = c->lay.S;
+    L.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
+    L.frozen = nullptr;
+    L.pair[0] = L.pair[1] = nullptr;
+    return L;
+}
+
+StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
+    StepArgs A;
+    A.src = c->lat[src];
+    A.dst = c->lat[src ^ 1];
+    A.nx = c->p.nx;
+    A.ny = c->p.ny;
+    A.nz = c->p.nz;
+    A.tiles_x = (c->p.nx + l.tile_x - 1) / l.tile_x;
+    A.tiles_y = (c->p.ny + l.tile_y - 1) / l.tile_y;
+    A.zchunk = l.zchunk < c->p.nz ? l.zchunk : c->p.nz;
+    A.nchunks = (c->p.nz + A.zchunk - 1) / A.zchunk;
+    A.pad_ = 0;
+    A.pop_stride = c->lay.S;
+    A.tau = c->p.tau;
+    A.G = c->p.G;
+    A.rho0 = c->p.rho0;
+    A.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
+    return A;
+}
+
+hipError_t plain_steps(lbm_ctx *c, int64_t n) {
+    const int ti = c->tile_index;
+    for (int64_t s = 0; s < n; ++s) {
+        const StepArgs A = step_args(c, c->launch, c->cur);
+        hipError_t e = launch_step(ti, c->p.storage, A, c->stream);
+        if (e != hipSuccess) return e;
+        c->cur ^= 1;
+        c->step += 1;
+    }
+    return hipSuccess;
+}
+
+void release_graph(lbm_ctx *c) {
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+}
+
+// Capture graph_chunk steps starting from lattice 0.
+hipError_t build_graph(lbm_ctx *c) {
+    release_graph(c);
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int s = 0; s < c->graph_chunk; ++s) {
+        const StepArgs A = step_args(c, c->launch, s & 1);
+        e = launch_step(c->tile_index, c->p.storage, A, c->stream);
+        if (e != hipSuccess) break;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    c->graph_launch = c->launch;
+    return e;
+}
+
+int get_fields_impl(lbm_ctx *c, const LatticeRef &L, const lbm_params &p, hipStream_t stream,
+                    uint32_t mask, double *rho, double *u, double *force, double *pop, int32_t on_device) {
+    const int64_t n = int64_t(p.nx) * p.ny * p.nz;
+    if (mask & ~uint32_t(LBM_FIELD_RHO | LBM_FIELD_U | LBM_FIELD_FORCE | LBM_FIELD_POP))
+        return fail(LBM_ERR_INVALID_ARG, "unknown field bits in mask 0x%x", mask);
+    if (((mask & LBM_FIELD_RHO) && !rho) || ((mask & LBM_FIELD_U) && !u) ||
+        ((mask & LBM_FIELD_FORCE) && !force) || ((mask & LBM_FIELD_POP) && !pop))
+        return fail(LBM_ERR_INVALID_ARG, "a requested field has a NULL pointer");
+    const bool need_rho = mask & (LBM_FIELD_RHO | LBM_FIELD_U | LBM_FIELD_FORCE);
+    // device destinations (either the caller's or temporaries)
+    double *d_rho = nullptr, *d_u = nullptr, *d_f = nullptr, *d_pop = nullptr;
+    std::vector<void *> temps;
+    auto temp = [&](size_t count, double **out) -> hipError_t {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(double));
+        if (e == hipSuccess) temps.push_back(q);
+        *out = static_cast<double *>(q);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    if (on_device) {
+        d_rho = (mask & LBM_FIELD_RHO) ? rho : nullptr;
+        d_u = (mask & LBM_FIELD_U) ? u : nullptr;
+        d_f = (mask & LBM_FIELD_FORCE) ? force : nullptr;
+        d_pop = (mask & LBM_FIELD_POP) ? pop : nullptr;
+        if (need_rho && !d_rho) e = temp(n, &d_rho);
+    } else {
+        if (need_rho && e == hipSuccess) e = temp(n, &d_rho);
+        if ((mask & LBM_FIELD_U) && e == hipSuccess) e = temp(3 * n, &d_u);
+        if ((mask & LBM_FIELD_FORCE) && e == hipSuccess) e = temp(3 * n, &d_f);
+        if ((mask & LBM_FIELD_POP) && e == hipSuccess) e = temp(size_t(Q) * n, &d_pop);
+    }
+    if (e == hipSuccess && need_rho) e = launch_export_rho(L, d_rho, stream);
+    if (e == hipSuccess && (d_u || d_f)) e = launch_export_force_u(L, d_rho, p.G, p.rho0, d_f, d_u, stream);
+    if (e == hipSuccess && d_pop) e = launch_export_pop(L, d_pop, stream);
+    if (e == hipSuccess && !on_device) {
+        if (mask & LBM_FIELD_RHO) e = hipMemcpyAsync(rho, d_rho, n * sizeof(double), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && (mask & LBM_FIELD_U))
+            e = hipMemcpyAsync(u, d_u, 3 * n * sizeof(double), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && (mask & LBM_FIELD_FORCE))
+            e = hipMemcpyAsync(force, d_f, 3 * n * sizeof(double), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && (mask & LBM_FIELD_POP))
+            e = hipMemcpyAsync(pop, d_pop, size_t(Q) * n * sizeof(double), hipMemcpyDeviceToHost, stream);
+    }
+    if (!temps.empty() || !on_device) {
+        hipError_t e2 = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = e2;
+    }
+    for (void *q : temps) (void)hipFree(q);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_get_fields");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+const char *lbm_version(void) { return "liblbm 0.1 (gfx950)"; }
+
+size_t lbm_workspace_bytes(const lbm_params *p) {
+    if (validate_params(p) != LBM_OK) return 0;
+    return layout_of(p).total;
+}
+
+int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
+    int st = validate_params(p);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    if (!d_workspace) return fail(LBM_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+        return fail(LBM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const Layout lay = layout_of(p);
+    if (ws_bytes < lay.total)
+        return fail(LBM_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, lay.total);
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char *>(d_workspace);
+    c->ws_bytes = ws_bytes;
+    c->lay = lay;
+    c->lat[0] = c->ws;
+    c->lat[1] = c->ws + lay.off_lat1;
+    c->partials = reinterpret_cast<DiagPartial *>(c->ws + lay.off_part);
+    c->slices = reinterpret_cast<unsigned long long *>(c->ws + lay.off_slices);
+    c->latest = reinterpret_cast<DiagRecord *>(c->ws + lay.off_latest);
+    c->ring = reinterpret_cast<DiagRecord *>(c->ws + lay.off_ring);
+    c->cur = 0;
+    c->axis = 2;
+    c->step = 0;
+    c->initialized = false;
+    c->poisoned = false;
+    c->ring_written = c->ring_read = 0;
+    c->graph_chunk = 0;
+    c->gexec = nullptr;
+    lbm_launch l;
+    if (!cache_lookup(tune_key(p), &l) || check_launch(&l, p->nz) != LBM_OK) l = default_launch(p);
+    c->launch = l;
+    c->tile_index = find_tile(l.tile_x, l.tile_y);
+    hipError_t e = launch_fill_u64(c->slices, lay.nslices, 0ull, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(LBM_ERR_DEVICE, "lbm_create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "context is NULL");
+    release_graph(c);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
+    if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
+    if (psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", psi);
+    if (!(tau > 0.5) || !isfinite(tau)) return fail(LBM_ERR_INVALID_ARG, "tau must be > 0.5");
+    if (!(rho0 > 0.0) || !isfinite(rho0)) return fail(LBM_ERR_INVALID_ARG, "rho0 must be > 0");
+    if (!(G < -4.0 / rho0) || !isfinite(G))
+        return fail(LBM_ERR_INVALID_ARG, "no liquid-vapour coexistence for G = %g (needs G < %g)", G, -4.0 / rho0);
+    const int n = 128, chunk = 1000, max_chunks = 200;
+    double *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(double) * (Q * n + 4));
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
+    double best = INFINITY, bl = 0, bv = 0;
+    int st = LBM_OK;
+    for (int k = 0; k < max_chunks; ++k) {
+        double out[4];
+        e = launch_coexistence_chunk(d, n, G, tau, rho0, chunk, k == 0, d + Q * n, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(out, d + Q * n, sizeof(out), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            st = fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
+            break;
+        }
+        if (out[3] != 0.0) {
+            if (!(best < INFINITY)) st = fail(LBM_ERR_DIVERGED, "flat interface diverged for G=%g tau=%g", G, tau);
+            break;
+        }
+        const double res = out[2];
+        if (res < best) {
+            best = res;
+            bl = out[0];
+            bv = out[1];
+        }
+        if (res < 1e-12 || (best < 1e-8 && res > 100.0 * best)) break;
+    }
+    (void)hipFree(d);
+    if (st != LBM_OK) return st;
+    *rho_l = bl;
+    *rho_v = bv;
+    return LBM_OK;
+}
+
+int lbm_init_ligament(lbm_ctx *c, const lbm_ligament *g) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!g) return fail(LBM_ERR_INVALID_ARG, "ligament spec is NULL");
+    if (g->axis < 0 || g->axis > 2) return fail(LBM_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
+    if (!(g->R0 > 0) || !(g->wavelength > 0) || !(g->width > 0) || !(g->noise_amp >= 0) ||
+        !isfinite(g->R0) || !isfinite(g->wavelength) || !isfinite(g->width) || !isfinite(g->amp_rel) ||
+        !isfinite(g->c1) || !isfinite(g->c2) || !isfinite(g->noise_amp))
+        return fail(LBM_ERR_INVALID_ARG, "ligament spec has a non-positive or non-finite field");
+    LigamentArgs a;
+    a.axis = g->axis;
+    a.R0 = g->R0;
+    a.amp_rel = g->amp_rel;
+    a.wavelength = g->wavelength;
+    a.c1 = g->c1;
+    a.c2 = g->c2;
+    a.width = g->width;
+    a.rho_l = g->rho_l;
+    a.rho_v = g->rho_v;
+    a.noise_amp = g->noise_amp;
+    a.seed = g->seed;
+    if (!(a.rho_l > 0) || !(a.rho_v > 0)) {
+        st = lbm_coexistence(c->p.G, c->p.tau, c->p.psi, c->p.rho0, &a.rho_l, &a.rho_v);
+        if (st != LBM_OK) return st;
+    }
+    hipError_t e = launch_init_ligament(lattice_ref(c, 0), a, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_init_ligament");
+    c->cur = 0;
+    c->step = 0;
+    c->initialized = true;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t nsteps) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    hipError_t e = hipSuccess;
+    int64_t left = nsteps;
+    if (c->graph_chunk > 0 && left >= c->graph_chunk) {
+        if (c->cur == 1) {
+            e = plain_steps(c, 1);
+            left -= 1;
+        }
+        if (e == hipSuccess && (!c->gexec || memcmp(&c->graph_launch, &c->launch, sizeof(lbm_launch)) != 0))
+            e = build_graph(c);
+        while (e == hipSuccess && left >= c->graph_chunk) {
+            e = hipGraphLaunch(c->gexec, c->stream);
+            c->step += c->graph_chunk;
+            left -= c->graph_chunk;
+        }
+    }
+    if (e == hipSuccess) e = plain_steps(c, left);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_step");
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_ctx *c, uint32_t mask, double *rho, double *u, double *force, double *pop,
+                   int32_t on_device) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    return get_fields_impl(c, lattice_ref(c, c->cur), c->p, c->stream, mask, rho, u, force, pop, on_device);
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *pop, int32_t on_device) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!pop) return fail(LBM_ERR_INVALID_ARG, "pop is NULL");
+    const int64_t n = int64_t(c->p.nx) * c->p.ny * c->p.nz;
+    hipError_t e = hipSuccess;
+    if (on_device) {
+        e = launch_import(lattice_ref(c, c->cur), pop, c->stream);
+    } else {
+        double *d = nullptr;
+        e = hipMalloc(&d, size_t(Q) * n * sizeof(double));
+        if (e == hipSuccess) e = hipMemcpyAsync(d, pop, size_t(Q) * n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_import(lattice_ref(c, c->cur), d, c->stream);
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = e2;
+        if (d) (void)hipFree(d);
+    }
+    if (e != hipSuccess) return device_fail(c, e, "lbm_set_populations");
+    c->initialized = true;
+    return LBM_OK;
+}
+
+static void to_public(const DiagRecord &r, lbm_diag *out) {
+    out->step = r.step;
+    out->mass = r.mass;
+    for (int d = 0; d < 3; ++d) out->mom[d] = r.mom[d];
+    out->rho_min = r.rho_min;
+    out->rho_max = r.rho_max;
+    out->neck_rho = r.neck_rho;
+    out->nonfinite = r.nonfinite;
+}
+
+int lbm_diagnostics(lbm_ctx *c, lbm_diag *out) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    DiagRecord r;
+    hipError_t e = launch_diag(lattice_ref(c, c->cur), c->axis, c->partials, c->slices, c->latest, c->step,
+                               nullptr, 0, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&r, c->latest, sizeof(r), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_diagnostics");
+    to_public(r, out);
+    if (r.nonfinite > 0)
+        return fail(LBM_ERR_DIVERGED, "%lld nodes non-finite or with rho <= 0 at step %lld",
+                    (long long)r.nonfinite, (long long)r.step);
+    return LBM_OK;
+}
+
+int lbm_set_axis(lbm_ctx *c, int32_t axis) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (axis < 0 || axis > 2) return fail(LBM_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
+    c->axis = axis;
+    return LBM_OK;
+}
+
+int lbm_record_diag(lbm_ctx *c) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    DiagRecord *slot = c->ring + (c->ring_written % LBM_DIAG_RING);
+    hipError_t e = launch_diag(lattice_ref(c, c->cur), c->axis, c->partials, c->slices, slot, c->step, nullptr, 0,
+                               c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_record_diag");
+    c->ring_written += 1;
+    return LBM_OK;
+}
+
+int lbm_read_diag_history(lbm_ctx *c, lbm_diag *out, int32_t max, int32_t *count) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!count || (max > 0 && !out) || max < 0) return fail(LBM_ERR_INVALID_ARG, "bad output arguments");
+    int64_t first = c->ring_read;
+    if (c->ring_written - first > LBM_DIAG_RING) first = c->ring_written - LBM_DIAG_RING;
+    int64_t avail = c->ring_written - first;
+    if (avail > max) avail = max;
+    std::vector<DiagRecord> host(LBM_DIAG_RING);
+    hipError_t e = hipMemcpyAsync(host.data(), c->ring, sizeof(DiagRecord) * LBM_DIAG_RING,
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_read_diag_history");
+    for (int64_t i = 0; i < avail; ++i) to_public(host[(first + i) % LBM_DIAG_RING], &out[i]);
+    c->ring_read = first + avail;
+    *count = int32_t(avail);
+    return LBM_OK;
+}
+
+int lbm_get_step(const lbm_ctx *c, int64_t *step) {
+    if (!c || !step) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+    *step = c->step;
+    return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx *c, const lbm_launch *l) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    st = check_launch(l, c->p.nz);
+    if (st != LBM_OK) return st;
+    c->launch = *l;
+    c->tile_index = find_tile(l->tile_x, l->tile_y);
+    return LBM_OK;
+}
+
+int lbm_get_launch(const lbm_ctx *c, lbm_launch *l) {
+    if (!c || !l) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+    *l = c->launch;
+    return LBM_OK;
+}
+
+int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count) {
+    if (!count || (max > 0 && !out) || max < 0) return fail(LBM_ERR_INVALID_ARG, "bad output arguments");
+    const int n = num_tiles();
+    for (int i = 0; i < n && i < max; ++i) {
+        tile_shape(i, &out[i].tile_x, &out[i].tile_y);
+        out[i].zchunk = 0;
+    }
+    *count = n;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, double *best_mlups) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    if (steps_per_candidate < 1) return fail(LBM_ERR_INVALID_ARG, "steps_per_candidate must be >= 1");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int zcs[] = {4, 8, 16, 32, 64, 128, 256};
+    double best_t = INFINITY;
+    lbm_launch bl = c->launch;
+    const double nodes = double(c->p.nx) * c->p.ny * c->p.nz;
+    for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
+        lbm_launch l;
+        tile_shape(ti, &l.tile_x, &l.tile_y);
+        if (l.tile_x > 2 * c->p.nx && l.tile_x > 32) continue;  // mostly idle lanes
+        for (int zc : zcs) {
+            if (zc > c->p.nz && zc != zcs[0]) break;
+            l.zchunk = zc;
+            const StepArgs A = step_args(c, l, c->cur);  // cur -> spare: state untouched
+            e = launch_step(ti, c->p.storage, A, c->stream);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
+                e = launch_step(ti, c->p.storage, A, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            const double t = ms / steps_per_candidate;
+            if (t < best_t) {
+                best_t = t;
+                bl = l;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return device_fail(c, e, "lbm_autotune");
+    c->launch = bl;
+    c->tile_index = find_tile(bl.tile_x, bl.tile_y);
+    cache_store(tune_key(&c->p), bl);
+    if (best) *best = bl;
+    if (best_mlups) *best_mlups = nodes / (best_t * 1e-3) / 1e6;
+    return LBM_OK;
+}
+
+int lbm_set_graph_chunk(lbm_ctx *c, int32_t chunk_steps) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (chunk_steps < 0 || (chunk_steps & 1)) return fail(LBM_ERR_INVALID_ARG, "chunk_steps must be even and >= 0");
+    if (chunk_steps > 0 && !c->stream)
+        return fail(LBM_ERR_UNSUPPORTED, "graph capture needs a non-null stream");
+    release_graph(c);
+    c->graph_chunk = chunk_steps;
+    return LBM_OK;
+}
+
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
+    if (!dst || !src) return fail(LBM_ERR_INVALID_ARG, "NULL pointer");
+    if (bytes % 16) return fail(LBM_ERR_INVALID_ARG, "bytes must be a multiple of 16");
+    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_device_copy: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form.
+//
+// Workspace: [case table][work items][frozen flags][diag records]
+//            [diag partials][slice maxima][lattice pairs of every case].
+// One launch per step processes the flat item list of all cases; a case's
+// frozen flag (set by the diagnostics on a non-finite or non-positive
+// density, to 1 + the lattice index current at that moment) makes its items
+// return immediately, so its state stays as it was when it was frozen.
+
+struct lbm_batch {
+    int n;
+    std::vector<lbm_params> p;
+    std::vector<Layout> lay;
+    std::vector<size_t> lat_off;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    BatchCase *d_cases;
+    int4 *d_items;
+    int32_t *d_frozen;
+    DiagRecord *d_records;
+    DiagPartial *d_partials;
+    unsigned long long *d_slices;
+    size_t item_capacity;
+    int nitems;
+    int parity;
+    int64_t step;
+    int check_every;
+    int64_t since_check;
+    bool initialized;
+    bool poisoned;
+    lbm_launch launch;
+    int tile_index;
+    int graph_chunk;
+    hipGraphExec_t gexec;
+    lbm_launch graph_launch;
+    int graph_parity;
+};
+
+namespace {
+
+constexpr int kBatchMinZchunk = 4;
+
+int64_t items_for(const lbm_params &p, int tx, int ty, int zc) {
+    const int64_t t = int64_t((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
+    const int z = zc < p.nz ? zc : p.nz;
+    return t * ((p.nz + z - 1) / z);
+}
+
+struct BatchLayout {
+    size_t off_cases, off_items, off_frozen, off_records, off_partials, off_slices, off_lat, total;
+    size_t item_capacity;
+    int max_parts, max_slices;
+    std::vector<Layout> lay;
+    std::vector<size_t> lat_off;
+};
+
+BatchLayout batch_layout(int n, const lbm_params *p) {
+    BatchLayout B;
+    B.item_capacity = 0;
+    B.max_parts = 1;
+    B.max_slices = 1;
+    for (int t = 0; t < num_tiles(); ++t) {
+        int tx, ty;
+        tile_shape(t, &tx, &ty);
+        size_t cnt = 0;
+        for (int i = 0; i < n; ++i) cnt += size_t(items_for(p[i], tx, ty, kBatchMinZchunk));
+        if (cnt > B.item_capacity) B.item_capacity = cnt;
+    }
+    for (int i = 0; i < n; ++i) {
+        B.lay.push_back(layout_of(&p[i]));
+        if (B.lay.back().nparts > B.max_parts) B.max_parts = B.lay.back().nparts;
+        if (B.lay.back().nslices > B.max_slices) B.max_slices = B.lay.back().nslices;
+    }
+    size_t off = 0;
+    B.off_cases = off;
+    off += align_up(sizeof(BatchCase) * n, 256);
+    B.off_items = off;
+    off += align_up(sizeof(int4) * B.item_capacity, 256);
+    B.off_frozen = off;
+    off += align_up(sizeof(int32_t) * n, 256);
+    B.off_records = off;
+    off += align_up(sizeof(DiagRecord) * n, 256);
+    B.off_partials = off;
+    off += align_up(sizeof(DiagPartial) * B.max_parts, 256);
+    B.off_slices = off;
+    off += align_up(sizeof(unsigned long long) * B.max_slices, 256);
+    B.off_lat = off;
+    for (int i = 0; i < n; ++i) {
+        B.lat_off.push_back(off);
+        off += 2 * B.lay[i].lat_bytes;
+    }
+    B.total = off;
+    return B;
+}
+
+int validate_batch(int n, const lbm_params *p) {
+    if (n < 1) return fail(LBM_ERR_INVALID_ARG, "a batch needs at least one case");
+    if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+    for (int i = 0; i < n; ++i) {
+        int st = validate_params(&p[i]);
+        if (st != LBM_OK) {
+            const std::string m = g_err;
+            return fail(st, "case %d: %s", i, m.c_str());
+        }
+        if (p[i].storage != p[0].storage)
+            return fail(LBM_ERR_INVALID_ARG, "case %d: all cases must share one storage kind", i);
+    }
+    return LBM_OK;
+}
+
+int batch_check(const lbm_batch *b) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (b->poisoned) return fail(LBM_ERR_STATE, "batch is poisoned by an earlier device error");
+    return LBM_OK;
+}
+
+int batch_device_fail(lbm_batch *b, hipError_t e, const char *what) {
+    b->poisoned = true;
+    return fail(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void *case_lat(const lbm_batch *b, int i, int which) {
+    return b->ws + b->lat_off[i] + (which ? b->lay[i].lat_bytes : 0);
+}
+
+LatticeRef batch_ref(const lbm_batch *b, int i, int which) {
+    LatticeRef L;
+    L.lat = case_lat(b, i, which);
+    L.nx = b->p[i].nx;
+    L.ny = b->p[i].ny;
+    L.nz = b->p[i].nz;
+    L.storage = b->p[i].storage;
+    L.pop_stride = b->lay[i].S;
+    L.rho_ref = is_shifted(b->p[i].storage) ? b->p[i].rho_ref : 0.0;
+    L.frozen = b->d_frozen + i;
+    L.pair[0] = case_lat(b, i, 0);
+    L.pair[1] = case_lat(b, i, 1);
+    return L;
+}
+
+// Rebuild the device case table and item list for the current launch shape.
+hipError_t batch_upload(lbm_batch *b) {
+    std::vector<BatchCase> cases(b->n);
+    std::vector<int4> items;
+    const lbm_launch &l = b->launch;
+    for (int i = 0; i < b->n; ++i) {
+        StepArgs A;
+        A.src = nullptr;
+        A.dst = nullptr;
+        A.nx = b->p[i].nx;
+        A.ny = b->p[i].ny;
+        A.nz = b->p[i].nz;
+        A.tiles_x = (A.nx + l.tile_x - 1) / l.tile_x;
+        A.tiles_y = (A.ny + l.tile_y - 1) / l.tile_y;
+        A.zchunk = l.zchunk < A.nz ? l.zchunk : A.nz;
+        A.nchunks = (A.nz + A.zchunk - 1) / A.zchunk;
+        A.pad_ = 0;
+        A.pop_stride = b->lay[i].S;
+        A.tau = b->p[i].tau;
+        A.G = b->p[i].G;
+        A.rho0 = b->p[i].rho0;
+        A.rho_ref = is_shifted(b->p[i].storage) ? b->p[i].rho_ref : 0.0;
+        cases[i].args = A;
+        cases[i].lat[0] = case_lat(b, i, 0);
+        cases[i].lat[1] = case_lat(b, i, 1);
+        // chunk-major, tile fastest: consecutive items are x-y neighbours of one case
+        for (int c = 0; c < A.nchunks; ++c)
+            for (int t = 0; t < A.tiles_x * A.tiles_y; ++t) items.push_back(make_int4(i, t, c, 0));
+    }
+    if (items.size() > b->item_capacity) return hipErrorInvalidValue;  // zchunk below the sized minimum
+    b->nitems = int(items.size());
+    hipError_t e = hipMemcpyAsync(b->d_cases, cases.data(), sizeof(BatchCase) * b->n, hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // host vectors die here
+    return e;
+}
+
+hipError_t batch_check_divergence(lbm_batch *b, DiagRecord *records) {
+    for (int i = 0; i < b->n; ++i) {
+        hipError_t e = launch_diag(batch_ref(b, i, b->parity), 2, b->d_partials, b->d_slices, records + i,
+                                   b->step, b->d_frozen + i, b->parity + 1, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t batch_plain(lbm_batch *b, int64_t n) {
+    for (int64_t s = 0; s < n; ++s) {
+        hipError_t e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
+                                         b->d_frozen, b->parity, b->stream);
+        if (e != hipSuccess) return e;
+        b->parity ^= 1;
+        b->step += 1;
+    }
+    return hipSuccess;
+}
+
+void batch_release_graph(lbm_batch *b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+}
+
+hipError_t batch_build_graph(lbm_batch *b) {
+    batch_release_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int s = 0; s < b->graph_chunk && e == hipSuccess; ++s)
+        e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
+                              s & 1, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    b->graph_launch = b->launch;
+    return e;
+}
+
+lbm_launch batch_default_launch(int n, const lbm_params *p) {
+    lbm_launch l;
+    int maxnx = 1;
+    for (int i = 0; i < n; ++i) maxnx = p[i].nx > maxnx ? p[i].nx : maxnx;
+    l.tile_x = maxnx >= 64 ? 64 : 32;
+    l.tile_y = 8;
+    l.zchunk = 16;
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(int32_t ncases, const lbm_params *p) {
+    if (validate_batch(ncases, p) != LBM_OK) return 0;
+    return batch_layout(ncases, p).total;
+}
+
+int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                     lbm_batch **out) {
+    int st = validate_batch(ncases, p);
+    if (st != LBM_OK) return st;
+    if (!out || !d_workspace) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+        return fail(LBM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    BatchLayout B = batch_layout(ncases, p);
+    if (ws_bytes < B.total)
+        return fail(LBM_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, B.total);
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
+    b->n = ncases;
+    b->p.assign(p, p + ncases);
+    b->lay = B.lay;
+    b->lat_off = B.lat_off;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->ws = static_cast<char *>(d_workspace);
+    b->ws_bytes = ws_bytes;
+    b->d_cases = reinterpret_cast<BatchCase *>(b->ws + B.off_cases);
+    b->d_items = reinterpret_cast<int4 *>(b->ws + B.off_items);
+    b->d_frozen = reinterpret_cast<int32_t *>(b->ws + B.off_frozen);
+    b->d_records = reinterpret_cast<DiagRecord *>(b->ws + B.off_records);
+    b->d_partials = reinterpret_cast<DiagPartial *>(b->ws + B.off_partials);
+    b->d_slices = reinterpret_cast<unsigned long long *>(b->ws + B.off_slices);
+    b->item_capacity = B.item_capacity;
+    b->parity = 0;
+    b->step = 0;
+    b->check_every = 1000;
+    b->since_check = 0;
+    b->initialized = false;
+    b->poisoned = false;
+    b->graph_chunk = 0;
+    b->gexec = nullptr;
+    b->launch = batch_default_launch(ncases, p);
+    b->tile_index = find_tile(b->launch.tile_x, b->launch.tile_y);
+    hipError_t e = launch_fill_u64(b->d_slices, B.max_slices, 0ull, b->stream);
+    if (e == hipSuccess) e = batch_upload(b);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(LBM_ERR_DEVICE, "lbm_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    batch_release_graph(b);
+    delete b;
+    return LBM_OK;
+}
+
+int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (!specs) return fail(LBM_ERR_INVALID_ARG, "specs is NULL");
+    std::vector<LigamentArgs> args(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        const lbm_ligament *g = &specs[i];
+        if (g->axis < 0 || g->axis > 2 || !(g->R0 > 0) || !(g->wavelength > 0) || !(g->width > 0) ||
+            !(g->noise_amp >= 0) || !isfinite(g->amp_rel) || !isfinite(g->c1) || !isfinite(g->c2))
+            return fail(LBM_ERR_INVALID_ARG, "case %d: invalid ligament spec", i);
+        LigamentArgs &a = args[i];
+        a.axis = g->axis;
+        a.R0 = g->R0;
+        a.amp_rel = g->amp_rel;
+        a.wavelength = g->wavelength;
+        a.c1 = g->c1;
+        a.c2 = g->c2;
+        a.width = g->width;
+        a.rho_l = g->rho_l;
+        a.rho_v = g->rho_v;
+        a.noise_amp = g->noise_amp;
+        a.seed = g->seed;
+        if (!(a.rho_l > 0) || !(a.rho_v > 0)) {
+            st = lbm_coexistence(b->p[i].G, b->p[i].tau, b->p[i].psi, b->p[i].rho0, &a.rho_l, &a.rho_v);
+            if (st != LBM_OK) {
+                const std::string m = g_err;
+                return fail(st, "case %d: %s", i, m.c_str());
+            }
+        }
+    }
+    hipError_t e = hipSuccess;
+    std::vector<int32_t> zeros(b->n, 0);
+    e = hipMemcpyAsync(b->d_frozen, zeros.data(), sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream);
+    for (int i = 0; i < b->n && e == hipSuccess; ++i) e = launch_init_ligament(batch_ref(b, i, 0), args[i], b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_init");
+    b->parity = 0;
+    b->step = 0;
+    b->since_check = 0;
+    b->initialized = true;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
+    hipError_t e = hipSuccess;
+    int64_t left = nsteps;
+    while (e == hipSuccess && left > 0) {
+        // run up to the next divergence check
+        int64_t run = b->check_every - b->since_check;
+        if (run > left) run = left;
+        int64_t r = run;
+        if (b->graph_chunk > 0 && r >= b->graph_chunk) {
+            if (b->parity == 1) {
+                e = batch_plain(b, 1);
+                r -= 1;
+            }
+            if (e == hipSuccess && (!b->gexec || memcmp(&b->graph_launch, &b->launch, sizeof(lbm_launch)) != 0))
+                e = batch_build_graph(b);
+            while (e == hipSuccess && r >= b->graph_chunk) {
+                e = hipGraphLaunch(b->gexec, b->stream);
+                b->step += b->graph_chunk;
+                r -= b->graph_chunk;
+            }
+        }
+        if (e == hipSuccess) e = batch_plain(b, r);
+        left -= run;
+        b->since_check += run;
+        if (e == hipSuccess && b->since_check >= b->check_every) {
+            e = batch_check_divergence(b, b->d_records);
+            b->since_check = 0;
+        }
+    }
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_step");
+    return LBM_OK;
+}
+
+int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
+    std::vector<DiagRecord> rec(b->n);
+    hipError_t e = batch_check_divergence(b, b->d_records);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rec.data(), b->d_records, sizeof(DiagRecord) * b->n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_diagnostics");
+    for (int i = 0; i < b->n; ++i) to_public(rec[i], &out[i]);
+    return LBM_OK;
+}
+
+int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho, double *u, double *force,
+                         double *pop, int32_t on_device) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (index < 0 || index >= b->n) return fail(LBM_ERR_INVALID_ARG, "case index %d out of range", index);
+    if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
+    int32_t fz = 0;
+    hipError_t e = hipMemcpyAsync(&fz, b->d_frozen + index, sizeof(fz), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_get_fields");
+    LatticeRef L = batch_ref(b, index, fz ? fz - 1 : b->parity);
+    L.frozen = nullptr;
+    st = get_fields_impl(nullptr, L, b->p[index], b->stream, mask, rho, u, force, pop, on_device);
+    if (st == LBM_ERR_DEVICE) b->poisoned = true;
+    return st;
+}
+
+int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    st = check_launch(l, 1);
+    if (st != LBM_OK) return st;
+    if (l->zchunk < kBatchMinZchunk) return fail(LBM_ERR_INVALID_ARG, "batched zchunk must be >= %d", kBatchMinZchunk);
+    b->launch = *l;
+    b->tile_index = find_tile(l->tile_x, l->tile_y);
+    hipError_t e = batch_upload(b);
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_set_launch");
+    return LBM_OK;
+}
+
+int lbm_batch_set_graph_chunk(lbm_batch *b, int32_t chunk_steps) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (chunk_steps < 0 || (chunk_steps & 1)) return fail(LBM_ERR_INVALID_ARG, "chunk_steps must be even and >= 0");
+    if (chunk_steps > 0 && !b->stream) return fail(LBM_ERR_UNSUPPORTED, "graph capture needs a non-null stream");
+    batch_release_graph(b);
+    b->graph_chunk = chunk_steps;
+    return LBM_OK;
+}
+
+}  // extern "C"

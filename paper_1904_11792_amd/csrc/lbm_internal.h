@@ -1,0 +1,95 @@
+// Internal interfaces between the host runtime (lbm_capi.hip) and the kernel
+// translation units of liblbm.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Arguments of one fused step launch over one grid.
+struct StepArgs {
+    const void *src;
+    void *dst;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, zchunk, nchunks;
+    int pad_;
+    int64_t pop_stride;  // elements between consecutive populations
+    double tau, G, rho0, rho_ref;
+};
+
+// One case of a batch: its step arguments (src/dst unset) and both lattices.
+struct BatchCase {
+    StepArgs args;
+    void *lat[2];
+};
+
+// Device record of one diagnostics evaluation (mirrors lbm_diag).
+struct DiagRecord {
+    int64_t step;
+    double mass, mom[3], rho_min, rho_max, neck_rho;
+    int64_t nonfinite;
+};
+
+// Per-block partial of the diagnostics reduction.
+struct DiagPartial {
+    double mass, mom[3], rho_min, rho_max;
+    double nonfinite;
+    double pad_;
+};
+
+// Description of a lattice for the auxiliary kernels.
+struct LatticeRef {
+    void *lat;
+    int nx, ny, nz;
+    int storage;
+    int64_t pop_stride;
+    double rho_ref;
+    // Batched cases only: when *frozen != 0 the state lives in pair[*frozen - 1]
+    // (the lattice current when the case was frozen) instead of lat.
+    const int32_t *frozen;
+    void *pair[2];
+};
+
+struct LigamentArgs {
+    int axis;
+    double R0, amp_rel, wavelength, c1, c2, width, rho_l, rho_v, noise_amp;
+    uint64_t seed;
+};
+
+// lbm_step.hip
+int num_tiles();
+void tile_shape(int i, int *tx, int *ty);
+int find_tile(int tx, int ty);
+hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s);
+hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
+                             const int4 *items, int nitems, const int32_t *frozen, int parity,
+                             hipStream_t s);
+
+// lbm_aux.hip
+hipError_t launch_init_ligament(const LatticeRef &L, const LigamentArgs &g, hipStream_t s);
+hipError_t launch_import(const LatticeRef &L, const double *pop, hipStream_t s);
+hipError_t launch_export_pop(const LatticeRef &L, double *pop, hipStream_t s);
+hipError_t launch_export_rho(const LatticeRef &L, double *rho, hipStream_t s);
+hipError_t launch_export_force_u(const LatticeRef &L, const double *rho, double G, double rho0,
+                                 double *force, double *u, hipStream_t s);
+// Number of partial slots the diagnostics reduction of this grid uses.
+int diag_blocks(int nx, int ny, int nz);
+// If frozen_flag is given and the state has a non-finite or non-positive
+// density, *frozen_flag is set to freeze_value unless it is already set.
+hipError_t launch_diag(const LatticeRef &L, int axis, DiagPartial *partials,
+                       unsigned long long *slice_max, DiagRecord *out, int64_t step,
+                       int32_t *frozen_flag, int32_t freeze_value, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long v,
+                           hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Flat-interface coexistence run: `chunk` steps on the 1 x 1 x n slab held in
+// `state` ([19][n] doubles); init != 0 first writes the start profile.
+// out[0] = rho(n/2), out[1] = rho(0), out[2] = max |rho - rho_before| over
+// the chunk, out[3] = 1 if a non-finite density appeared.
+hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
+                                    int chunk, int init, double *out, hipStream_t s);
+
+}  // namespace lbm

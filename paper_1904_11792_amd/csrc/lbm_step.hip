@@ -1,0 +1,198 @@
+// Fused Shan-Chen D3Q19 step for gfx950: psi, force, collision and streaming
+// of one time step in a single kernel (Section 2, Eqs. 2-6).
+//
+// Layout: structure of arrays, population a of node i at a * S + i (S = the
+// population stride, a multiple of 64 elements), i = ((z * ny) + y) * nx + x.
+// Streaming is PULL between two lattices: the launch reads src and writes dst,
+// and a node gathers f_a(x, t) = src_a(x - c_a), i.e. src holds the
+// post-collision values of the previous step at their source nodes.
+//
+// The psi stencil of Eq. (5) needs psi, hence rho, of all 18 neighbours at
+// the same time level.  Each workgroup owns a tile_x * tile_y column of the
+// grid (one thread per node) and marches it over `zchunk` planes along z.
+// Per plane it gathers the populations of its tile (kept in registers for the
+// collision one plane later) and of a one-node ring around the tile (only
+// their density is kept), and writes psi into a four-plane window in LDS; the
+// force then reads psi(z-1), psi(z), psi(z+1) from LDS.  HBM traffic stays at
+// 19 loads + 19 stores per node: the ring and the two extra planes of a z
+// chunk are re-reads of lines that neighbouring tiles, scheduled on the same
+// XCD at the same time, have just brought into L2.
+#include "lbm_internal.h"
+
+namespace lbm {
+
+template <int ST, int TX, int TY>
+__device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk) {
+    using Tr = Storage<ST>;
+    using T = typename Tr::T;
+    using C = typename Tr::C;
+    constexpr int PX = TX + 2;
+    constexpr int PY = TY + 2;
+    constexpr int RING = 2 * PX + 2 * TY;
+    static_assert(RING <= TX * TY, "ring must fit the thread count");
+    __shared__ C win[4][PY][PX];
+
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
+    const int plane = nx * ny;
+    const T *__restrict__ src = static_cast<const T *>(A.src);
+    T *__restrict__ dst = static_cast<T *>(A.dst);
+    const int64_t S = A.pop_stride;
+    const C rho0 = C(A.rho0), inv_rho0 = C(1.0 / A.rho0);
+    const C G = C(A.G), tau = C(A.tau), omega = C(1.0 / A.tau);
+    C shift[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) shift[a] = Tr::kShifted ? C(weight(a) * A.rho_ref) : C(0);
+
+    const int x0 = tile_x * TX, y0 = tile_y * TY;
+    const int z0 = chunk * A.zchunk;
+    const int kend = min(A.zchunk, nz - z0);
+
+    const int t = threadIdx.x;
+    const int lx = t % TX, ly = t / TX;
+    const bool active = (x0 + lx < nx) && (y0 + ly < ny);
+    // Source columns/rows of the pull: index (1 - c) selects x - c.
+    const int gx = wrapi(x0 + lx, nx), gy = wrapi(y0 + ly, ny);
+    const int X[3] = {wrapi(gx - 1, nx), gx, wrapi(gx + 1, nx)};
+    const int Y[3] = {wrapi(gy - 1, ny) * nx, gy * nx, wrapi(gy + 1, ny) * nx};
+
+    // Ring node handled by this thread (t < RING), in tile coordinates [-1, TX] x [-1, TY].
+    const bool ring = t < RING;
+    int rx = 0, ry = 0;
+    if (t < PX) {
+        rx = t - 1;
+        ry = -1;
+    } else if (t < 2 * PX) {
+        rx = t - PX - 1;
+        ry = TY;
+    } else {
+        const int r = t - 2 * PX;
+        rx = (r < TY) ? -1 : TX;
+        ry = (r < TY) ? r : r - TY;
+    }
+    const int rgx = wrapi(x0 + rx, nx), rgy = wrapi(y0 + ry, ny);
+    const int RX[3] = {wrapi(rgx - 1, nx), rgx, wrapi(rgx + 1, nx)};
+    const int RY[3] = {wrapi(rgy - 1, ny) * nx, rgy * nx, wrapi(rgy + 1, ny) * nx};
+
+    auto gather = [&](int zc, const int(&XX)[3], const int(&YY)[3], C(&f)[Q]) {
+        const int Z[3] = {wrapi(zc - 1, nz) * plane, zc * plane, wrapi(zc + 1, nz) * plane};
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const int off = Z[1 - kCZ[a]] + YY[1 - kCY[a]] + XX[1 - kCX[a]];
+            f[a] = Tr::decode(src[a * S + off], shift[a]);
+        }
+    };
+    // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
+    auto load_plane = [&](int zc, int s, C(&f)[Q]) {
+        gather(zc, X, Y, f);
+        win[s][ly + 1][lx + 1] = pseudo_potential(density(f), rho0, inv_rho0);
+        if (ring) {
+            C g[Q];
+            gather(zc, RX, RY, g);
+            win[s][ry + 1][rx + 1] = pseudo_potential(density(g), rho0, inv_rho0);
+        }
+    };
+
+    C cur[Q], nxt[Q];
+    load_plane(wrapi(z0 - 1, nz), 3, nxt);
+    load_plane(z0, 0, cur);
+
+    for (int k = 0; k < kend; ++k) {
+        const int zc = z0 + k;
+        load_plane(wrapi(zc + 1, nz), (k + 1) & 3, nxt);
+        __syncthreads();
+        if (active) {
+            const int sm = (k + 3) & 3, s0 = k & 3, sp = (k + 1) & 3;
+            auto P = [&](int dx, int dy, int dz) -> C {
+                const int s = dz < 0 ? sm : (dz > 0 ? sp : s0);
+                return win[s][ly + 1 + dy][lx + 1 + dx];
+            };
+            C Fx, Fy, Fz;
+            sc_force<C>(win[s0][ly + 1][lx + 1], G, P, Fx, Fy, Fz);
+            collide<C>(cur, Fx, Fy, Fz, tau, omega);
+            const int o = zc * plane + Y[1] + X[1];
+#pragma unroll
+            for (int a = 0; a < Q; ++a)
+                __builtin_nontemporal_store(Tr::encode(cur[a], shift[a]), &dst[a * S + o]);
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) cur[a] = nxt[a];
+    }
+}
+
+template <int ST, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_step(StepArgs A) {
+    const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int ntile = A.tiles_x * A.tiles_y;
+    const int tile = lb % ntile, chunk = lb / ntile;
+    step_tile<ST, TX, TY>(A, tile % A.tiles_x, tile / A.tiles_x, chunk);
+}
+
+// Batched form: one launch covers every case's work items.  Items are
+// (case, tile, chunk) triples; case parameters and lattice pointers come from
+// a device table; frozen cases are skipped.
+template <int ST, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_step_batch(const BatchCase *__restrict__ cases,
+                                                       const int4 *__restrict__ items,
+                                                       const int32_t *__restrict__ frozen,
+                                                       int parity) {
+    const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int4 it = items[lb];
+    if (frozen[it.x]) return;
+    const BatchCase &bc = cases[it.x];
+    StepArgs A = bc.args;
+    A.src = bc.lat[parity];
+    A.dst = bc.lat[parity ^ 1];
+    step_tile<ST, TX, TY>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z);
+}
+
+// ---------------------------------------------------------------------------
+// Launch tables.
+
+struct TileEntry {
+    int tx, ty;
+    const void *fn[4];
+    const void *batch_fn[4];
+};
+
+#define LBM_TILE(TXV, TYV)                                                                   \
+    {TXV, TYV,                                                                               \
+     {(const void *)k_step<kF64, TXV, TYV>, (const void *)k_step<kF32, TXV, TYV>,           \
+      (const void *)k_step<kF16S, TXV, TYV>, (const void *)k_step<kBF16S, TXV, TYV>},       \
+     {(const void *)k_step_batch<kF64, TXV, TYV>, (const void *)k_step_batch<kF32, TXV, TYV>, \
+      (const void *)k_step_batch<kF16S, TXV, TYV>,                                          \
+      (const void *)k_step_batch<kBF16S, TXV, TYV>}}
+
+static const TileEntry kTiles[] = {
+    LBM_TILE(64, 4), LBM_TILE(64, 8), LBM_TILE(64, 16), LBM_TILE(32, 8),
+    LBM_TILE(32, 16), LBM_TILE(128, 4), LBM_TILE(128, 8),
+};
+#undef LBM_TILE
+
+int num_tiles() { return int(sizeof(kTiles) / sizeof(kTiles[0])); }
+void tile_shape(int i, int *tx, int *ty) {
+    *tx = kTiles[i].tx;
+    *ty = kTiles[i].ty;
+}
+int find_tile(int tx, int ty) {
+    for (int i = 0; i < num_tiles(); ++i)
+        if (kTiles[i].tx == tx && kTiles[i].ty == ty) return i;
+    return -1;
+}
+
+hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s) {
+    const TileEntry &e = kTiles[tile_index];
+    const int nblk = A.tiles_x * A.tiles_y * A.nchunks;
+    StepArgs args = A;
+    void *kargs[] = {&args};
+    return hipLaunchKernel(e.fn[storage], dim3(nblk), dim3(e.tx * e.ty), kargs, 0, s);
+}
+
+hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
+                             const int4 *items, int nitems, const int32_t *frozen, int parity,
+                             hipStream_t s) {
+    const TileEntry &e = kTiles[tile_index];
+    void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity};
+    return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(e.tx * e.ty), kargs, 0, s);
+}
+
+}  // namespace lbm

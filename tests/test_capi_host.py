@@ -1,0 +1,104 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+declared entry point, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "liblbm.h")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_1904_11792_amd import lbm as mod
+
+    return mod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    names = declared_functions()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_version_and_tiles(lbm):
+    assert "gfx950" in lbm.lbm_version()
+    tiles = lbm.lbm_list_tiles()
+    assert (64, 8) in tiles and (32, 8) in tiles
+    for tx, ty in tiles:
+        assert tx % 16 == 0 and tx * ty <= 1024
+
+
+def test_workspace_bytes_and_validation(lbm):
+    p = lbm.make_params(256, 256, 1024, 0.8, -5.5, storage="f32")
+    nb = lbm.lbm_workspace_bytes(p)
+    assert nb >= 2 * 19 * 256 * 256 * 1024 * 4
+    assert nb < 2 * 19 * 256 * 256 * 1024 * 4 * 1.01
+    p16 = lbm.make_params(256, 256, 1024, 0.8, -5.5, storage="f16s")
+    assert lbm.lbm_workspace_bytes(p16) < nb / 1.9
+    bad = [lbm.make_params(0, 4, 4, 0.8, -5.5), lbm.make_params(4, 4, 4, 0.5, -5.5),
+           lbm.make_params(4, 4, 4, float("nan"), -5.5), lbm.make_params(4, 4, 4, 0.8, float("inf")),
+           lbm.make_params(4, 4, 4, 0.8, -5.5, rho0=0.0), lbm.make_params(4, 4, 4, 0.8, -5.5, storage=7),
+           lbm.make_params(2048, 2048, 1024, 0.8, -5.5)]
+    for q in bad:
+        assert lbm.lbm_workspace_bytes(q) == 0
+        assert lbm.lbm_last_error() != ""
+
+
+def test_create_rejects_bad_arguments_before_device_work(lbm):
+    p = lbm.make_params(8, 8, 8, 0.8, -5.5, storage="f32")
+    need = lbm.lbm_workspace_bytes(p)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, 0x100000, need - 1, 0)
+    assert e.value.status == lbm.LBM_ERR_BUFFER_TOO_SMALL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, 0x100001, need, 0)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, 0, need, 0)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    q = lbm.make_params(8, 8, 8, 0.4, -5.5)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(q, 0x100000, need, 0)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    assert "tau" in e.value.message
+
+
+def test_coexistence_rejects_subcritical_and_bad_tau(lbm):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_coexistence(-3.5, 1.0)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_coexistence(-5.5, 0.5)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_coexistence(-5.5, 1.0, psi=3)
+    assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
+
+
+def test_null_handles_are_rejected(lbm):
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_step(None, 1)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_destroy(None)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_diagnostics(None)
+
+
+def test_batch_validation(lbm):
+    ps = [lbm.make_params(24, 24, 40, 0.8, -5.5, storage="f32"),
+          lbm.make_params(30, 30, 50, 0.9, -5.2, storage="f64")]
+    arr = (lbm.lbm_params * 2)(*ps)
+    assert lbm._lib.lbm_batch_workspace_bytes(2, arr) == 0
+    assert "storage" in lbm.lbm_last_error()
+    ok = (lbm.lbm_params * 1)(ps[0])
+    assert lbm._lib.lbm_batch_workspace_bytes(1, ok) > 2 * 19 * 24 * 24 * 40 * 4

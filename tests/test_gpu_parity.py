@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every case runs the same seeded input through liblbm (ctypes binding, torch
+device memory) and through the oracle, and compares element by element.
+Bars (from the method's specification): FP64 populations within 1e-11
+relative after 200 steps; FP32 density within 1e-5 relative after 200 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+RHO_L, RHO_V = 2.3068, 0.1041  # near-coexistence inputs at G = -5.5, tau = 1
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_11792_amd import lbm as mod
+
+    return mod
+
+
+def _ligament_pair(lbm, oracle_mod, nx, ny, nz, tau, G, storage="f64", **spec):
+    spec.setdefault("rho_l", RHO_L)
+    spec.setdefault("rho_v", RHO_V)
+    f0 = oracle_mod.init_ligament(nx, ny, nz, **spec)
+    lat = lbm.Lattice(nx, ny, nz, tau, G, storage=storage, rho_ref=spec["rho_v"])
+    lat.init_ligament(**spec)
+    return f0, lat
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def test_init_matches_oracle(lbm, oracle_mod):
+    spec = dict(R0=5.0, amp_rel=0.1, wavelength=20.0, noise_amp=1e-4, seed=77)
+    for axis in (0, 1, 2):
+        f0, lat = _ligament_pair(lbm, oracle_mod, 18, 22, 20, 0.9, -5.5, axis=axis, **spec)
+        got = lat.populations().cpu().numpy()
+        assert _relerr(got, f0) < 1e-14, axis  # tanh, cos and sqrt ulps
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 64), (17, 23, 29), (70, 12, 20), (1, 1, 64),
+                                   (5, 7, 3), (33, 9, 70)])
+def test_fp64_step_parity_200(lbm, oracle_mod, shape):
+    nx, ny, nz = shape
+    R0 = max(1.5, min(nx, ny) / 4)
+    spec = dict(R0=R0, amp_rel=0.1, wavelength=float(nz), noise_amp=1e-3, seed=5)
+    if nx == 1:  # quasi-1D: a flat slab along z
+        spec = dict(axis=0, R0=nz / 4, amp_rel=0.0, wavelength=1.0, c1=0.0, c2=nz / 2 - 0.5,
+                    noise_amp=1e-3, seed=5)
+    f0, lat = _ligament_pair(lbm, oracle_mod, nx, ny, nz, 1.0, -5.5, **spec)
+    ref = oracle_mod.run(f0, 200, 1.0, -5.5)
+    lat.step(200)
+    got = lat.populations().cpu().numpy()
+    assert np.all(np.isfinite(ref))
+    assert _relerr(got, ref) < 1e-11
+
+
+def test_fp64_every_tile_shape(lbm, oracle_mod):
+    """Each compiled tile, with z chunks that leave a ragged tail, on a ragged grid."""
+    nx, ny, nz = 75, 21, 23
+    spec = dict(R0=6.0, amp_rel=0.15, wavelength=23.0, noise_amp=1e-3, seed=8)
+    f0 = oracle_mod.init_ligament(nx, ny, nz, rho_l=RHO_L, rho_v=RHO_V, **spec)
+    ref = oracle_mod.run(f0, 6, 0.85, -5.5)
+    for tx, ty in lbm.lbm_list_tiles():
+        for zc in (1, 5, 23, 40):
+            lat = lbm.Lattice(nx, ny, nz, 0.85, -5.5, storage="f64")
+            lat.set_launch(tx, ty, zc)
+            lat.init_ligament(rho_l=RHO_L, rho_v=RHO_V, **spec)
+            lat.step(6)
+            got = lat.populations().cpu().numpy()
+            assert _relerr(got, ref) < 1e-13, (tx, ty, zc)
+            lat.close()
+
+
+def test_fp64_generic_state_via_import(lbm, oracle_mod):
+    f = workloads.random_populations((9, 10, 11), seed=4, base=1.3, spread=0.5)
+    lat = lbm.Lattice(11, 10, 9, 0.7, -5.0, storage="f64")
+    lat.set_populations(f)
+    back = lat.populations().cpu().numpy()
+    assert np.array_equal(back, f)
+    lat.step(30)
+    ref = oracle_mod.run(f, 30, 0.7, -5.0)
+    assert _relerr(lat.populations().cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["small tau=1", "large-like tau=0.8"])
+def test_fp32_density_parity_200(lbm, oracle_mod, case):
+    if case == "small tau=1":
+        s = workloads.SMALL_FP64
+        nx, ny, nz, tau, G = s.nx, s.ny, s.nz, s.tau, s.G
+        spec = dict(R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength)
+    else:  # the large FP32 ligament's parameters on a 64 x 64 x 96 grid
+        nx, ny, nz, tau, G = 64, 64, 96, 0.8, -5.5
+        spec = dict(R0=10.0, amp_rel=0.05, wavelength=96.0, noise_amp=1e-4, seed=1,
+                    rho_l=2.2726, rho_v=0.0742)
+    f0, lat = _ligament_pair(lbm, oracle_mod, nx, ny, nz, tau, G, storage="f32", **spec)
+    lat.step(200)
+    ref = oracle_mod.run(f0, 200, tau, G).sum(axis=0)
+    rho = lat.fields()["rho"].cpu().numpy()
+    assert _relerr(rho, ref) < 1e-5
+
+
+def test_fields_match_oracle(lbm, oracle_mod):
+    f0, lat = _ligament_pair(lbm, oracle_mod, 20, 18, 24, 0.8, -5.5, R0=5.0, amp_rel=0.1,
+                             wavelength=24.0, noise_amp=1e-3, seed=2)
+    lat.step(15)
+    ref_f = oracle_mod.run(f0, 15, 0.8, -5.5)
+    ref = oracle_mod.fields(ref_f, -5.5)
+    got = {k: v.cpu().numpy() for k, v in lat.fields(rho=True, u=True, force=True).items()}
+    assert _relerr(got["rho"], ref["rho"]) < 1e-12
+    scale_u = np.abs(ref["u"]).max()
+    scale_f = np.abs(ref["F"]).max()
+    assert np.max(np.abs(got["u"] - ref["u"])) < 1e-11 * scale_u
+    assert np.max(np.abs(got["force"] - ref["F"])) < 1e-11 * scale_f
+
+
+def test_diagnostics_match_oracle(lbm, oracle_mod):
+    f0, lat = _ligament_pair(lbm, oracle_mod, 24, 20, 30, 0.9, -5.5, R0=5.0, amp_rel=0.2,
+                             wavelength=30.0, noise_amp=1e-3, seed=1)
+    lat.step(40)
+    ref = oracle_mod.diag(oracle_mod.run(f0, 40, 0.9, -5.5))
+    for axis in (2, 1, 0):
+        lat.set_axis(axis)
+        d = lat.diagnostics()
+        r = oracle_mod.diag(oracle_mod.run(f0, 40, 0.9, -5.5), axis=axis)
+        assert d["step"] == 40
+        assert d["mass"] == pytest.approx(r["mass"], rel=1e-13)
+        assert np.allclose(d["mom"], r["mom"], atol=1e-11)
+        assert d["rho_min"] == pytest.approx(r["rho_min"], rel=1e-12)
+        assert d["rho_max"] == pytest.approx(r["rho_max"], rel=1e-12)
+        assert d["neck_rho"] == pytest.approx(r["neck_rho"], rel=1e-12)
+        assert d["nonfinite"] == 0 and not d["diverged"]
+    del ref
+
+
+def test_mass_conservation_fp64(lbm):
+    s = workloads.SMALL_FP64
+    lat = lbm.Lattice(s.nx, s.ny, s.nz, s.tau, s.G, storage="f64")
+    lat.init_ligament(R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength, rho_l=RHO_L, rho_v=RHO_V)
+    m0 = lat.diagnostics()["mass"]
+    lat.step(2000)
+    d = lat.diagnostics()
+    assert abs(d["mass"] - m0) / m0 < 1e-13
+    assert np.all(np.abs(d["mom"]) < 1e-10)
+
+
+def test_diag_history_ring(lbm):
+    lat = lbm.Lattice(16, 16, 32, 1.0, -5.5, storage="f32")
+    lat.init_ligament(R0=4.0, amp_rel=0.1, wavelength=32.0, rho_l=RHO_L, rho_v=RHO_V)
+    for _ in range(5):
+        lat.step(3)
+        lat.record_diag()
+    h = lat.read_diag_history()
+    assert [r["step"] for r in h] == [3, 6, 9, 12, 15]
+    assert lat.read_diag_history() == []
+    final = lat.diagnostics()
+    assert final["mass"] == h[-1]["mass"]
+
+
+def test_coexistence_matches_oracle(lbm, oracle_mod):
+    for G, tau in [(-5.5, 1.0), (-5.5, 0.8), (-6.0, 1.0)]:
+        rl, rv = lbm.lbm_coexistence(G, tau)
+        co = oracle_mod.coexistence(G, tau)
+        assert rl == pytest.approx(co.rho_l, rel=1e-9), (G, tau)
+        assert rv == pytest.approx(co.rho_v, rel=1e-8), (G, tau)
+
+
+def test_graph_replay_equals_plain_launches(lbm):
+    import torch
+
+    spec = dict(R0=5.0, amp_rel=0.1, wavelength=32.0, rho_l=RHO_L, rho_v=RHO_V, noise_amp=1e-3, seed=3)
+    s = torch.cuda.Stream()
+    a = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage="f32", stream=s)
+    b = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage="f32", stream=s)
+    a.init_ligament(**spec)
+    b.init_ligament(**spec)
+    b.set_graph_chunk(10)
+    for k in range(3):  # several replays, with eager work between them
+        a.step(25)
+        b.step(25)
+        pa = a.populations().cpu().numpy()
+        pb = b.populations().cpu().numpy()
+        assert np.array_equal(pa, pb), k
+
+
+def test_translation_equivariance_on_gpu(lbm):
+    """A periodic shift of the input shifts the output bitwise (no tile-dependent arithmetic)."""
+    f = workloads.random_populations((20, 18, 70), seed=6, base=1.0, spread=0.3)
+    a = lbm.Lattice(70, 18, 20, 0.8, -5.5, storage="f32")
+    b = lbm.Lattice(70, 18, 20, 0.8, -5.5, storage="f32")
+    a.set_populations(f)
+    b.set_populations(np.roll(f, (3, 5, 37), axis=(1, 2, 3)))
+    a.step(10)
+    b.step(10)
+    pa = a.populations().cpu().numpy()
+    pb = b.populations().cpu().numpy()
+    assert np.array_equal(np.roll(pa, (3, 5, 37), axis=(1, 2, 3)), pb)
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_shifted_storage_error_bounded(lbm, oracle_mod, storage):
+    """FP16/BF16 shifted storage: density error vs the FP64 oracle after 200 steps is reported and bounded."""
+    s = workloads.SMALL_FP64
+    f0, lat = _ligament_pair(lbm, oracle_mod, s.nx, s.ny, s.nz, s.tau, s.G, storage=storage,
+                             R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength)
+    m0 = lat.diagnostics()["mass"]
+    lat.step(200)
+    ref = oracle_mod.run(f0, 200, s.tau, s.G).sum(axis=0)
+    rho = lat.fields()["rho"].cpu().numpy()
+    err = _relerr(rho, ref)
+    drift = abs(lat.diagnostics()["mass"] - m0) / m0
+    print(f"{storage}: max rel density error after 200 steps {err:.3e}, mass drift {drift:.3e}")
+    bound = 2e-2 if storage == "f16s" else 1e-1
+    assert err < bound
+    assert drift < 1e-2
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_shifted_storage_round_trip_is_exact(lbm, storage):
+    """Values that are w_a rho_ref + (a representable number) survive encode/decode exactly."""
+    import torch
+
+    oracle_w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    rho_ref = 0.25
+    dt = torch.float16 if storage == "f16s" else torch.bfloat16
+    h = torch.tensor(workloads.random_populations((3, 4, 5), seed=2, base=1.0, spread=0.9),
+                     dtype=torch.float64).to(dt).to(torch.float32)
+    pop = (torch.tensor(oracle_w, dtype=torch.float32)[:, None, None, None] * rho_ref + h).double()
+    lat = lbm.Lattice(5, 4, 3, 0.8, -5.5, storage=storage, rho_ref=rho_ref)
+    lat.set_populations(pop.numpy())
+    back = lat.populations().cpu()
+    assert torch.equal(back, pop)
+
+
+def test_batch_case_equals_single_run(lbm):
+    cases = workloads.batch64(seed=7, count=5)
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
+                               rho_l=RHO_L, rho_v=RHO_V, seed=c.seed) for c in cases]
+    b = lbm.Batch(params)
+    b.init(specs)
+    b.step(30)
+    for i, c in enumerate(cases):
+        single = lbm.Lattice(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32")
+        tx, ty, zc = b_launch = (32 if max(p.nx for p in params) < 64 else 64, 8, 16)
+        single.set_launch(tx, ty, zc)
+        single.init_ligament(R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength, rho_l=RHO_L,
+                             rho_v=RHO_V, seed=c.seed)
+        single.step(30)
+        pb = b.fields(i, rho=False, pop=True)["pop"].cpu().numpy()
+        ps = single.populations().cpu().numpy()
+        assert np.array_equal(pb, ps), (i, b_launch)
+        single.close()
