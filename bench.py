@@ -54,6 +54,40 @@ def measured_traffic(storage: str, nodes: int):
     return e.get("bytes_per_launch")
 
 
+STORAGE_ID = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+
+
+def traffic_from_counters(fetch_csv: str, write_csv: str, storage: str) -> dict:
+    """HBM bytes per launch of the fused step from two rocprofv3 --pmc runs of
+    this benchmark (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each
+    counter is scaled by what it reads for the plain copy kernel of the same
+    run, whose bytes are known (19 n b read and written)."""
+    import csv
+
+    spec = __import__("workloads").LARGE_FP32
+    copy_kib = 19 * spec.n * BYTES_PER_POP[storage] / 1024.0
+    tag = f"k_step<{STORAGE_ID[storage]},"
+
+    def per_dispatch(path, counter):
+        step, copy = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            if tag in r["Kernel_Name"]:
+                step.append(float(r["Counter_Value"]))
+            elif "k_copy16" in r["Kernel_Name"]:
+                copy.append(float(r["Counter_Value"]))
+        return sum(step) / len(step), sum(copy) / len(copy)
+
+    fs, fc = per_dispatch(fetch_csv, "FETCH_SIZE")
+    ws, wc = per_dispatch(write_csv, "WRITE_SIZE")
+    fscale, wscale = copy_kib / fc, copy_kib / wc
+    total = (fs * fscale + ws * wscale) * 1024.0
+    return {"kernel_digest": kernel_digest(), "nodes": spec.n, "bytes_per_launch": round(total),
+            "bytes_per_node": round(total / spec.n, 2), "fetch_scale": round(fscale, 4),
+            "write_scale": round(wscale, 4), "fetch_kib_raw": fs, "write_kib_raw": ws}
+
+
 def cpu_baseline(spec, rho_l, rho_v, budget_s=12.0):
     """The FP64 oracle on a z-slab of the same ligament (bounded sample)."""
     import oracle
@@ -86,7 +120,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        try:
+            table = json.load(open(TRAFFIC_FILE))
+        except (OSError, ValueError):
+            table = {}
+        table[args.storage] = traffic_from_counters(*args.traffic_from, args.storage)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(table, fh, indent=1)
+        print(json.dumps(table[args.storage]))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU z-slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)

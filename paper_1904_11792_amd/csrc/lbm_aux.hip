@@ -26,28 +26,29 @@ __device__ inline int64_t node_index(int x, int y, int z, int nx, int ny) {
              x += kBlock)                                                            \
             if (const int64_t i = int64_t(row) * (L).nx + x; true)
 
-// Index of lattice slot holding f_a(x, t) under pull streaming: x - c_a.
+// Element offset of population a at the lattice site that holds f_a(x, t)
+// under pull streaming: site x - c_a.
 __device__ inline int64_t pull_source(int a, int x, int y, int z, const LatticeRef &L) {
-    return node_index(wrapi(x - kCX[a], L.nx), wrapi(y - kCY[a], L.ny), wrapi(z - kCZ[a], L.nz),
-                      L.nx, L.ny);
+    return a * L.pop_stride + int64_t(wrapi(z - kCZ[a], L.nz)) * L.plane_stride +
+           int64_t(wrapi(y - kCY[a], L.ny)) * L.row_stride + wrapi(x - kCX[a], L.nx);
 }
 
 template <int ST>
-__device__ inline double read_pop(const LatticeRef &L, int a, int64_t slot) {
+__device__ inline double read_pop(const LatticeRef &L, int a, int64_t off) {
     using Tr = Storage<ST>;
     using C = typename Tr::C;
     const auto *p = static_cast<const typename Tr::T *>(L.lat);
     const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
-    return double(Tr::decode(p[a * L.pop_stride + slot], shift));
+    return double(Tr::decode(p[off], shift));
 }
 
 template <int ST>
-__device__ inline void write_pop(const LatticeRef &L, int a, int64_t slot, double v) {
+__device__ inline void write_pop(const LatticeRef &L, int a, int64_t off, double v) {
     using Tr = Storage<ST>;
     using C = typename Tr::C;
     auto *p = static_cast<typename Tr::T *>(L.lat);
     const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
-    p[a * L.pop_stride + slot] = Tr::encode(C(v), shift);
+    p[off] = Tr::encode(C(v), shift);
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014) used counter-based: first output of
@@ -78,12 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_init_ligament(LatticeRef L, Ligament
             rho += g.noise_amp * (2.0 * U - 1.0);
         }
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            // f_a(x) lives at slot x - c_a
-            const int64_t slot = node_index(wrapi(x - kCX[a], L.nx), wrapi(y - kCY[a], L.ny),
-                                            wrapi(z - kCZ[a], L.nz), L.nx, L.ny);
-            write_pop<ST>(L, a, slot, weight(a) * rho);
-        }
+        for (int a = 0; a < Q; ++a) write_pop<ST>(L, a, pull_source(a, x, y, z, L), weight(a) * rho);
     }
 }
 

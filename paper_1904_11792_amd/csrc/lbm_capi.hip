@@ -47,8 +47,9 @@ int validate_params(const lbm_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    if (n > int64_t(0x7fffffff))
-        return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1", (long long)n);
+    if (n * Q > int64_t(0x7fffffff))
+        return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes is too large for 32-bit site offsets",
+                    (long long)n);
     if (!(p->tau > 0.5) || !isfinite(p->tau))
         return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 0.5 (got %g)", p->tau);
     if (!isfinite(p->G)) return fail(LBM_ERR_INVALID_ARG, "G must be finite");
@@ -62,7 +63,8 @@ int validate_params(const lbm_params *p) {
 }
 
 struct Layout {
-    int64_t S;
+    int64_t S;       // population stride (elements)
+    int R, P;        // row and plane strides (elements)
     size_t lat_bytes, off_lat1, off_part, off_slices, off_latest, off_ring, total;
     int nparts, nslices;
 };
@@ -70,8 +72,14 @@ struct Layout {
 Layout layout_of(const lbm_params *p) {
     Layout L;
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    L.S = (n + 63) / 64 * 64;
-    L.lat_bytes = align_up(size_t(Q) * L.S * elem_bytes(p->storage), 256);
+    // Row-interleaved [z][y][a][x]: the 19 population segments of one grid
+    // row are contiguous (population stride nx, row stride 19 nx, plane
+    // stride 19 nx ny).
+    L.S = p->nx;
+    L.R = Q * p->nx;
+    L.P = Q * p->nx * p->ny;
+    const int64_t cells = int64_t(Q) * n;
+    L.lat_bytes = align_up(size_t(cells) * elem_bytes(p->storage), 256);
     L.off_lat1 = L.lat_bytes;
     L.nparts = diag_blocks(p->nx, p->ny, p->nz);
     L.nslices = p->nx > p->ny ? (p->nx > p->nz ? p->nx : p->nz) : (p->ny > p->nz ? p->ny : p->nz);
@@ -158,14 +166,24 @@ void cache_store(const std::string &key, const lbm_launch &l) {
     rename(tmp.c_str(), path);
 }
 
-// Default launch shape: widest tile that does not overhang x by more than
-// half, and enough z chunks for a few thousand workgroups.
+// Default launch shape: the widest compiled tile that fits the x extent
+// (whole rows of the row-interleaved layout stream best), and about one
+// workgroup per compute unit (256) by choosing the z chunk.
 lbm_launch default_launch(const lbm_params *p) {
     lbm_launch l;
-    l.tile_x = p->nx >= 64 ? 64 : 32;
-    l.tile_y = 8;
+    if (p->nx >= 256) {
+        l.tile_x = 256; l.tile_y = 4;
+    } else if (p->nx >= 128) {
+        l.tile_x = 128; l.tile_y = 8;
+    } else if (p->nx >= 64) {
+        l.tile_x = 64; l.tile_y = 16;
+    } else if (p->nx >= 32) {
+        l.tile_x = 32; l.tile_y = 16;
+    } else {
+        l.tile_x = 16; l.tile_y = 16;
+    }
     const int64_t tiles = int64_t((p->nx + l.tile_x - 1) / l.tile_x) * ((p->ny + l.tile_y - 1) / l.tile_y);
-    int64_t chunks = (2048 + tiles - 1) / tiles;
+    int64_t chunks = (256 + tiles - 1) / tiles;
     int64_t zc = (p->nz + chunks - 1) / chunks;
     if (zc < 4) zc = 4;
     if (zc > p->nz) zc = p->nz;
@@ -229,6 +247,8 @@ LatticeRef lattice_ref(const lbm_ctx *c, int which) {
     L.nz = c->p.nz;
     L.storage = c->p.storage;
     L.pop_stride = c->lay.S;
+    L.row_stride = c->lay.R;
+    L.plane_stride = c->lay.P;
     L.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
     L.frozen = nullptr;
     L.pair[0] = L.pair[1] = nullptr;
@@ -248,6 +268,8 @@ StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
     A.nchunks = (c->p.nz + A.zchunk - 1) / A.zchunk;
     A.pad_ = 0;
     A.pop_stride = c->lay.S;
+    A.row_stride = c->lay.R;
+    A.plane_stride = c->lay.P;
     A.tau = c->p.tau;
     A.G = c->p.G;
     A.rho0 = c->p.rho0;
@@ -841,6 +863,8 @@ LatticeRef batch_ref(const lbm_batch *b, int i, int which) {
     L.nz = b->p[i].nz;
     L.storage = b->p[i].storage;
     L.pop_stride = b->lay[i].S;
+    L.row_stride = b->lay[i].R;
+    L.plane_stride = b->lay[i].P;
     L.rho_ref = is_shifted(b->p[i].storage) ? b->p[i].rho_ref : 0.0;
     L.frozen = b->d_frozen + i;
     L.pair[0] = case_lat(b, i, 0);
@@ -866,6 +890,8 @@ hipError_t batch_upload(lbm_batch *b) {
         A.nchunks = (A.nz + A.zchunk - 1) / A.zchunk;
         A.pad_ = 0;
         A.pop_stride = b->lay[i].S;
+        A.row_stride = b->lay[i].R;
+        A.plane_stride = b->lay[i].P;
         A.tau = b->p[i].tau;
         A.G = b->p[i].G;
         A.rho0 = b->p[i].rho0;

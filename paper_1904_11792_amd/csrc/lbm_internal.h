@@ -16,7 +16,11 @@ struct StepArgs {
     int nx, ny, nz;
     int tiles_x, tiles_y, zchunk, nchunks;
     int pad_;
-    int64_t pop_stride;  // elements between consecutive populations
+    // element offset of population a at node (x, y, z):
+    //   a * pop_stride + z * plane_stride + y * row_stride + x
+    // (the node part, z * plane_stride + y * row_stride + x, fits in 32 bits)
+    int64_t pop_stride;
+    int row_stride, plane_stride;
     double tau, G, rho0, rho_ref;
 };
 
@@ -46,6 +50,7 @@ struct LatticeRef {
     int nx, ny, nz;
     int storage;
     int64_t pop_stride;
+    int row_stride, plane_stride;
     double rho_ref;
     // Batched cases only: when *frozen != 0 the state lives in pair[*frozen - 1]
     // (the lattice current when the case was frozen) instead of lat.
