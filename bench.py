@@ -116,10 +116,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
-    ap.add_argument("--form", default="single", choices=["single", "batch"])
+    ap.add_argument("--form", default="single",
+                    choices=["single", "batch", "precision", "convergence"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every compiled tile and a set of z chunks, print a markdown table")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
@@ -148,6 +151,10 @@ def main():
     stream = torch.cuda.Stream(dev)
     if args.form == "batch":
         return bench_batch(args, lbm, workloads, stream)
+    if args.form == "precision":
+        return study_precision(args, lbm, workloads, stream)
+    if args.form == "convergence":
+        return study_convergence(args, lbm, workloads, stream)
 
     spec = workloads.LARGE_FP32
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
@@ -156,6 +163,8 @@ def main():
                       rho_ref=rho_v, stream=stream)
     lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength,
                       rho_l=rho_l, rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
+    if args.sweep:
+        return sweep(lat, spec, stream, args.storage)
     if args.launch:
         lat.set_launch(*[int(v) for v in args.launch.split(",")])
     if args.graph_chunk:
@@ -210,6 +219,132 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, rho_l, rho_v)
     print(json.dumps(out), flush=True)
+
+
+def sweep(lat, spec, stream, storage):
+    """Per-launch time of every compiled tile shape and several z chunks."""
+    import torch
+
+    from paper_1904_11792_amd import lbm
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    zcs = (32, 64, 128, 256)
+    bpn = 2 * 19 * BYTES_PER_POP[storage]
+    print(f"| tile | " + " | ".join(f"z {z} ms" for z in zcs) + " | best GB/s |")
+    print("|---|" + "---:|" * (len(zcs) + 1))
+    for tx, ty in lbm.lbm_list_tiles():
+        row = []
+        for zc in zcs:
+            lat.set_launch(tx, ty, zc)
+            lat.step(3)
+            e0.record(stream)
+            lat.step(10)
+            e1.record(stream)
+            e1.synchronize()
+            row.append(e0.elapsed_time(e1) / 10)
+        best = min(row)
+        print(f"| {tx}x{ty} | " + " | ".join(f"{v:.3f}" for v in row) +
+              f" | {bpn * spec.n / best / 1e6:.0f} |", flush=True)
+
+
+def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, extra_after=0):
+    """Step one ligament to break-up (neck sampled every `every` steps), then
+    `extra_after` more steps; returns t_b, time per step, droplets, mass drift."""
+    import torch
+
+    from paper_1904_11792_amd import analysis
+
+    lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage, rho_ref=rho_v,
+                      stream=stream)
+    lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength, rho_l=rho_l,
+                      rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
+    m0 = lat.diagnostics()["mass"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    tb, steps, neck, last = analysis.run_to_breakup(lat, rho_l, rho_v, max_steps, every=every)
+    e1.record(stream)
+    e1.synchronize()
+    n_done = lat.step_count
+    ms_step = e0.elapsed_time(e1) / max(n_done, 1)
+    if extra_after:
+        lat.step(extra_after)
+    d = lat.diagnostics()
+    rho = lat.fields()["rho"].cpu().numpy()
+    drops = analysis.droplets(rho, 0.5 * (rho_l + rho_v))
+    lat.close()
+    return {"t_b": tb, "steps": lat.step_count if False else n_done + extra_after,
+            "ms_per_step_incl_diag": round(ms_step, 4),
+            "droplets": drops.count, "volumes": drops.volumes[:8].tolist(),
+            "mass_drift": (d["mass"] - m0) / m0, "nonfinite": d["nonfinite"]}
+
+
+def study_precision(args, lbm, workloads, stream):
+    """Shifted FP16/BF16 storage against FP32 and FP64 on the large ligament
+    (and a stronger-attraction case): break-up time, droplets, mass drift and
+    step throughput.  The FP64 GPU run is the reference (itself held to the
+    oracle within 1e-11 over 200 steps by the parity tests)."""
+    import dataclasses
+
+    import torch
+
+    base = workloads.LARGE_FP32
+    cases = [base, dataclasses.replace(base, name="large G=-6.0", G=-6.0)]
+    out = []
+    for spec in cases:
+        rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+        res = {}
+        for storage in ("f64", "f32", "f16s", "bf16s"):
+            print(f"# {spec.name} {storage}", file=sys.stderr, flush=True)
+            r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, spec.steps, every=10,
+                              extra_after=1000)
+            # pure step throughput (no diagnostics) on the same grid
+            lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage,
+                              rho_ref=rho_v, stream=stream)
+            lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength,
+                              rho_l=rho_l, rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
+            lat.step(5)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(50)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / 50
+            lat.close()
+            r["ms_per_step"] = round(ms, 4)
+            r["MLUPS"] = round(spec.n / ms / 1e3, 1)
+            res[storage] = r
+            print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
+        ref = res["f64"]["t_b"]
+        for st, r in res.items():
+            r["t_b_rel_err_vs_f64"] = None if (ref is None or r["t_b"] is None) else (r["t_b"] - ref) / ref
+        out.append({"case": spec.name, "G": spec.G, "tau": spec.tau, "rho_l": rho_l, "rho_v": rho_v,
+                    "results": res})
+    print(json.dumps({"study": "precision", "grid": [base.nx, base.ny, base.nz], "cases": out}))
+
+
+def study_convergence(args, lbm, workloads, stream):
+    """Grid-convergence series: break-up time over the capillary time against
+    1/R for R = 8, 16, 32, 64 in FP32 and FP64 (sigma from Laplace runs)."""
+    from paper_1904_11792_amd import analysis
+
+    G, tau = -5.5, 1.0
+    rho_l, rho_v = lbm.lbm_coexistence(G, tau)
+    sigma, icpt = analysis.laplace_sigma(lbm, G, tau, rho_l, rho_v)
+    rows = []
+    for R in (8, 16, 32, 64):
+        spec = workloads.convergence(R)
+        tcap = analysis.capillary_time(rho_l, R, sigma)
+        for storage in ("f32", "f64"):
+            print(f"# R={R} {storage}", file=sys.stderr, flush=True)
+            r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps=int(40 * tcap) + 2000,
+                              every=max(1, R // 8))
+            r.update({"R": R, "grid": [spec.nx, spec.ny, spec.nz], "storage": storage,
+                      "t_cap": tcap, "t_b_over_t_cap": None if r["t_b"] is None else r["t_b"] / tcap,
+                      "kR": 2 * 3.141592653589793 * R / spec.nz})
+            rows.append(r)
+            print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "convergence", "G": G, "tau": tau, "rho_l": rho_l, "rho_v": rho_v,
+                      "sigma": sigma, "laplace_intercept": icpt, "rows": rows}))
 
 
 def bench_batch(args, lbm, workloads, stream):

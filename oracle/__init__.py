@@ -257,3 +257,48 @@ def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
         if res < tol or (best[0] < 1e-8 and res > 100.0 * best[0]):
             break
     return Coexistence(best[2], best[3], best[1], best[0], best[0] < tol)
+
+
+def breakup_time(steps, neck, rho_mid: float):
+    """First sample where the neck density drops below rho_mid, with linear
+    interpolation between that sample and the one before it; None if never."""
+    prev = None
+    for t, v in zip(steps, neck):
+        if v < rho_mid:
+            if prev is None:
+                return float(t)
+            t0, v0 = prev
+            return float(t0) + (v0 - rho_mid) / (v0 - v) * (float(t) - float(t0))
+        prev = (t, v)
+    return None
+
+
+def droplets(rho: np.ndarray, rho_mid: float):
+    """(count, volumes, masses) of the 6-connected periodic components of
+    rho > rho_mid, largest volume first."""
+    count, lab = label(rho, rho_mid)
+    vols = np.zeros(count, dtype=np.int64)
+    mass = np.zeros(count)
+    flat_l = lab.ravel()
+    flat_r = np.asarray(rho, dtype=np.float64).ravel()
+    for i in range(flat_l.size):
+        c = flat_l[i]
+        if c:
+            vols[c - 1] += 1
+            mass[c - 1] += flat_r[i]
+    order = np.argsort(-vols, kind="stable")
+    return count, vols[order], mass[order]
+
+
+def run_to_breakup(f: np.ndarray, tau: float, G: float, rho_mid: float, max_steps: int,
+                   every: int = 1, rho0: float = 1.0, axis: int = 2):
+    """Step the oracle, sampling the neck density every `every` steps, until it
+    falls below rho_mid or max_steps.  Returns (t_b or None, steps, necks, f)."""
+    steps, necks = [0], [diag(f, axis)["neck_rho"]]
+    t = 0
+    while t < max_steps and necks[-1] >= rho_mid:
+        f = run(f, every, tau, G, rho0)
+        t += every
+        steps.append(t)
+        necks.append(diag(f, axis)["neck_rho"])
+    return breakup_time(steps, necks, rho_mid), steps, necks, f

@@ -316,10 +316,22 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long *p, size
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Streaming copy: each thread moves four 16-byte vectors spaced one block
+// apart (coalesced), loads first, then non-temporal stores.
 __global__ __launch_bounds__(kBlock) void k_copy16(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
                                                    size_t count) {
-    for (size_t i = blockIdx.x * size_t(kBlock) + threadIdx.x; i < count; i += size_t(gridDim.x) * kBlock)
-        __builtin_nontemporal_store(src[i], &dst[i]);
+    const size_t base = blockIdx.x * size_t(4 * kBlock) + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + size_t(k) * kBlock;
+        if (i < count) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + size_t(k) * kBlock;
+        if (i < count) __builtin_nontemporal_store(v[k], &dst[i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -483,10 +495,10 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long lo
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
     const size_t count = bytes / 16;
-    int64_t nb = int64_t((count + kBlock - 1) / kBlock);
-    if (nb > 256 * 64) nb = 256 * 64;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_copy16, dim3(nb), dim3(kBlock), 0, s, (u32x4 *)dst, (const u32x4 *)src, count);
+    const size_t nb = (count + 4 * kBlock - 1) / (4 * kBlock);
+    if (nb == 0) return hipSuccess;
+    if (nb > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy16, dim3(unsigned(nb)), dim3(kBlock), 0, s, (u32x4 *)dst, (const u32x4 *)src, count);
     return hipGetLastError();
 }
 
