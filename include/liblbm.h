@@ -99,19 +99,32 @@ int lbm_destroy(lbm_ctx *ctx);
 
 /*
  * Coexisting liquid/vapour densities for (G, tau, psi, rho0), in FP64 on the
- * current HIP device: a flat interface on a 1 x 1 x 128 periodic slab
- * (liquid on [32, 96), tanh start of width 4 between densities 2.1 rho0 and
- * 0.1 rho0, at rest) is advanced in chunks of 1000 steps of the same update
- * (Eqs. 2-6) until the largest density change over a chunk is below 1e-12,
- * until that change has grown 100-fold above its smallest value once the
- * smallest is below 1e-8, or for 200 chunks; the densities at z = 64
- * (liquid) and z = 0 (vapour) of the chunk with the smallest change are
- * returned.  With the velocity-shift forcing they depend on tau as well as
- * G.  Synchronous.  Errors: INVALID_ARG (G >= -4 has no coexistence for
- * psi_exp with rho0 = 1, tau <= 0.5, null outputs), DIVERGED, DEVICE.
+ * current HIP device.  A flat interface on a 1 x 1 x 128 periodic slab
+ * (liquid on [32, 96), tanh start of width 4 between the densities of
+ * lbm_equal_area, at rest) is advanced in chunks of 1000 steps of the same
+ * update (Eqs. 2-6).  For tau < 1 it is first relaxed at tau = 1 and at tau
+ * lowered in steps of 0.05 (each stage until the largest density change over
+ * a chunk is below 1e-8, at most 100 chunks), because a direct low-tau start
+ * can blow up in its initial transient.  At the requested tau it runs until
+ * the chunk change is below 1e-12, until that change has grown 100-fold
+ * above its smallest value once the smallest is below 1e-8, or for 200
+ * chunks; the densities at z = 64 (liquid) and z = 0 (vapour) of the chunk
+ * with the smallest change are returned.  With the velocity-shift forcing
+ * they depend on tau as well as G.  Synchronous.  Errors: INVALID_ARG
+ * (G >= -4/rho0 has no coexistence, tau <= 0.5, null outputs), DIVERGED,
+ * DEVICE.
  */
 int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l,
                     double *rho_v);
+
+/*
+ * Equal-area (mechanical stability) construction for the equation of state
+ * of Eq. (7), P = rho c_s^2 + c_s^2 G psi^2 / 2: the densities with
+ * P(rho_v) = P(rho_l) = p whose integral of (p - P) psi'/psi^2 between them
+ * vanishes.  Host-only arithmetic (no device work); the start of
+ * lbm_coexistence.  Errors: INVALID_ARG for G >= -4/rho0 (no coexistence).
+ */
+int lbm_equal_area(double G, int32_t psi, double rho0, double *rho_l, double *rho_v);
 
 /*
  * Ligament initial condition (Section 3, Fig. 1): a liquid cylinder along
@@ -259,6 +272,12 @@ typedef struct lbm_batch lbm_batch;
 size_t lbm_batch_workspace_bytes(int32_t ncases, const lbm_params *p);
 int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, size_t ws_bytes,
                      void *hip_stream, lbm_batch **out);
+/*
+ * Set up every case (lbm_init_ligament semantics).  A case whose densities
+ * are to come from lbm_coexistence but whose flat interface diverges at its
+ * (G, tau) starts frozen with non-finite densities instead of failing the
+ * whole batch.
+ */
 int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs);
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Per-case diagnostics (synchronises); frozen cases report nonfinite > 0. */
@@ -267,6 +286,13 @@ int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out);
 int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho, double *u,
                          double *force, double *pop, int32_t on_device);
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
+/*
+ * Autotuner of the batched launch: time each tile shape and z chunk (>= 4)
+ * over the whole item list (launches from the current lattices into the
+ * spare ones, so the state is unchanged) and keep the fastest.  Synchronous.
+ */
+int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *best,
+                       double *best_mlups);
 int lbm_batch_set_graph_chunk(lbm_batch *b, int32_t chunk_steps);
 int lbm_batch_destroy(lbm_batch *b);
 

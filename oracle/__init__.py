@@ -20,6 +20,7 @@ Arrays are numpy float64 with shape (19, nz, ny, nx), C-contiguous.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -218,21 +219,70 @@ class Coexistence:
     converged: bool
 
 
+def equal_area(G: float, rho0: float = 1.0):
+    """Liquid/vapour densities of the Shan-Chen mechanical-stability
+    construction for the EOS of Eq. (7): P(rho_v) = P(rho_l) = p and
+    integral_{rho_v}^{rho_l} (p - P) psi'/psi^2 drho = 0.  The spinodals are
+    closed-form (psi psi' = rho0 e (1 - e) with e = exp(-rho/rho0)); the
+    roots and the pressure are found by bracketing (scipy brentq, quad)."""
+    from scipy import integrate, optimize
+
+    if not G < -4.0 / rho0:
+        raise ValueError("no coexistence above the critical point")
+    P = lambda r: pressure(r, G, rho0)
+    root = math.sqrt(1.0 + 4.0 / (G * rho0))
+    s_lo = -rho0 * math.log(0.5 * (1.0 + root))   # spinodal on the vapour side
+    s_hi = -rho0 * math.log(0.5 * (1.0 - root))   # spinodal on the liquid side
+
+    def branches(p):
+        rv = optimize.brentq(lambda r: P(r) - p, 0.0, s_lo, xtol=1e-15)
+        top = 3.0 * (p - G * rho0 * rho0 / 6.0) + 10.0
+        rl = optimize.brentq(lambda r: P(r) - p, s_hi, top, xtol=1e-15)
+        return rv, rl
+
+    def area(p):
+        rv, rl = branches(p)
+        f = lambda r: (p - P(r)) * math.exp(-r / rho0) / psi(r, rho0) ** 2
+        return integrate.quad(f, rv, rl, epsabs=1e-13, epsrel=1e-10, limit=400)[0]
+
+    # the vapour branch exists only for p > 0 = P(0)
+    lo, hi = max(P(s_hi), 0.0), P(s_lo)
+    eps = 1e-12 * (hi - lo)
+    p = optimize.brentq(area, lo + eps, hi - eps, xtol=1e-15)
+    rv, rl = branches(p)
+    return rl, rv
+
+
 def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
                 tol: float = 1e-12, chunk: int = 1000, max_steps: int = 200_000,
-                rho_hi: float = 2.1, rho_lo: float = 0.1, width: float = 4.0) -> Coexistence:
+                rho_hi: float | None = None, rho_lo: float | None = None,
+                width: float = 4.0, tau_step: float = 0.05) -> Coexistence:
     """Coexisting densities from a flat interface on a 1 x 1 x n periodic slab.
 
-    Start: rho = lo + (hi - lo)/2 [tanh(2(z - z1)/W) - tanh(2(z - z2)/W)] with
+    Start: densities hi/lo of the equal-area construction (``equal_area``)
+    unless given, profile
+    rho = lo + (hi - lo)/2 [tanh(2(z - z1)/W) - tanh(2(z - z2)/W)] with
     z1 = n/4 - 1/2 and z2 = 3n/4 - 1/2 (liquid on [n/4, 3n/4)), populations at
-    rest equilibrium.  The run proceeds in chunks; the residual of a chunk is
-    the largest density change over it.  It stops when the residual is below
-    ``tol``, when it has grown 100-fold above the smallest residual seen once
-    that one is below 1e-8 (the quasi-1D slab at tau = 1 develops a slowly
-    growing counter-flow drift seeded by round-off), or at ``max_steps``.  The state with the smallest
-    residual is reported: liquid density at z = n/2, vapour at z = 0.
-    The velocity-shift forcing makes these depend on tau as well as on G.
+    rest equilibrium.
+
+    For tau < 1 the slab is first relaxed at tau = 1 and then at tau lowered
+    in steps of ``tau_step`` (each of these stages until the largest density
+    change over a chunk is below 1e-8, at most 100 chunks): starting a
+    low-tau run directly from the construction's densities can blow up in
+    the initial transient, while each stage starts close to its own steady
+    state.
+
+    The final stage at the requested tau runs in chunks; the residual of a
+    chunk is the largest density change over it.  It stops when the residual
+    is below ``tol``, when it has grown 100-fold above the smallest residual
+    seen once that one is below 1e-8 (the quasi-1D slab at tau = 1 develops a
+    slowly growing counter-flow drift seeded by round-off), or at
+    ``max_steps``.  The state with the smallest residual is reported: liquid
+    density at z = n/2, vapour at z = 0.  The velocity-shift forcing makes
+    these depend on tau as well as on G.
     """
+    if rho_hi is None or rho_lo is None:
+        rho_hi, rho_lo = equal_area(G, rho0)
     z = np.arange(n, dtype=np.float64)
     z1, z2 = n / 4 - 0.5, 3 * n / 4 - 0.5
     rho = rho_lo + (rho_hi - rho_lo) * 0.5 * (np.tanh(2.0 * (z - z1) / width)
@@ -241,14 +291,33 @@ def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
     f = np.empty((Q, n, 1, 1))
     for a in range(Q):
         f[a, :, 0, 0] = w[a] * rho
+    stages = []
+    if tau < 1.0:
+        t = 1.0
+        while t > tau + 1e-12:
+            stages.append(t)
+            t = round(t - tau_step, 12)
+    diverged = Coexistence(float("nan"), float("nan"), 0, float("inf"), False)
     prev = rho.copy()
-    best = (np.inf, 0, float(rho[n // 2]), float(rho[0]))
+    for t in stages:  # relaxation stages
+        for _ in range(100):
+            f = run(f, chunk, t, G, rho0)
+            cur = f.sum(axis=0)[:, 0, 0]
+            if not np.all(np.isfinite(cur)):
+                return diverged
+            res = float(np.max(np.abs(cur - prev)))
+            prev = cur
+            if res < 1e-8:
+                break
+    best = (np.inf, 0, float(prev[n // 2]), float(prev[0]))
     steps = 0
     while steps < max_steps:
         f = run(f, chunk, tau, G, rho0)
         steps += chunk
         cur = f.sum(axis=0)[:, 0, 0]
         if not np.all(np.isfinite(cur)):
+            if best[0] == np.inf:
+                return diverged
             break
         res = float(np.max(np.abs(cur - prev)))
         prev = cur

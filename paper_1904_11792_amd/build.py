@@ -1,6 +1,7 @@
 """Build liblbm.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1904_11792_amd.build   (always recompiles)
+Usage: python paper_1904_11792_amd/build.py   (always recompiles; run it by
+path -- importing the package loads the library it builds)
 """
 from __future__ import annotations
 

@@ -340,8 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_copy16(u32x4 *__restrict__ dst, cons
 // so the same force stencil and collision as the 3-D step apply unchanged.
 // State convention here: f_a(z, t) at z (push streaming inside LDS).
 __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state, int n, double G,
-                                                      double tau, double rho0, int chunk, int init,
-                                                      double *__restrict__ out) {
+                                                      double tau, double rho0, double hi, double lo,
+                                                      int chunk, int init, double *__restrict__ out) {
     extern __shared__ double sm[];
     double *fa = sm;              // [19][n]
     double *fb = sm + Q * n;      // [19][n]
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state
     const double inv_rho0 = 1.0 / rho0, omega = 1.0 / tau;
     if (z < n) {
         if (init) {
-            const double hi = 2.1 * rho0, lo = 0.1 * rho0, W = 4.0;
+            const double W = 4.0;
             const double z1 = n / 4 - 0.5, z2 = 3 * (n / 4) - 0.5;
             const double rho = lo + (hi - lo) * 0.5 * (tanh(2.0 * (z - z1) / W) - tanh(2.0 * (z - z2) / W));
             for (int a = 0; a < Q; ++a) fa[a * n + z] = weight(a) * rho;
@@ -503,9 +503,11 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) 
 }
 
 hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    int chunk, int init, double *out, hipStream_t s) {
+                                    double hi, double lo, int chunk, int init, double *out,
+                                    hipStream_t s) {
     const size_t lds = sizeof(double) * (2 * Q * n + 2 * n);
-    hipLaunchKernelGGL(k_coexistence, dim3(1), dim3(n), lds, s, state, n, G, tau, rho0, chunk, init, out);
+    hipLaunchKernelGGL(k_coexistence, dim3(1), dim3(n), lds, s, state, n, G, tau, rho0, hi, lo, chunk,
+                       init, out);
     return hipGetLastError();
 }
 

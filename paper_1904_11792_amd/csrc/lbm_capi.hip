@@ -432,6 +432,77 @@ int lbm_destroy(lbm_ctx *c) {
     return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Equal-area (mechanical stability) construction of the Shan-Chen EOS,
+// P = rho/3 + G psi^2/6 (Eq. 7), psi = rho0 (1 - exp(-rho/rho0)):
+// P(rho_v) = P(rho_l) = p and the integral of (p - P) psi'/psi^2 from rho_v
+// to rho_l vanishes.  Spinodals in closed form, branches and p by bisection,
+// the integral by composite Simpson.  Used as the start of the flat-interface
+// run.  Requires G < -4/rho0.
+struct EqualArea {
+    double G, rho0;
+    double psi(double r) const { return -rho0 * expm1(-r / rho0); }
+    double P(double r) const {
+        const double s = psi(r);
+        return r / 3.0 + G * s * s / 6.0;
+    }
+    template <typename F>
+    static double bisect(F f, double a, double b) {  // f(a) < 0 < f(b)
+        for (int i = 0; i < 200 && b - a > 1e-15 * (1.0 + fabs(b)); ++i) {
+            const double m = 0.5 * (a + b);
+            (f(m) < 0 ? a : b) = m;
+        }
+        return 0.5 * (a + b);
+    }
+    void solve(double *rl, double *rv) const {
+        const double root = sqrt(1.0 + 4.0 / (G * rho0));
+        const double s_lo = -rho0 * log(0.5 * (1.0 + root));
+        const double s_hi = -rho0 * log(0.5 * (1.0 - root));
+        auto branches = [&](double p, double *v, double *l) {
+            *v = bisect([&](double r) { return P(r) - p; }, 0.0, s_lo);
+            const double top = 3.0 * (p - G * rho0 * rho0 / 6.0) + 10.0;
+            *l = bisect([&](double r) { return P(r) - p; }, s_hi, top);
+        };
+        // Simpson in u = ln(rho) (drho = rho du), where the integrand is smooth
+        // down to small vapour densities.
+        auto area = [&](double p) {
+            double v, l;
+            branches(p, &v, &l);
+            const int N = 4000;
+            const double u0 = log(v), h = (log(l) - u0) / N;
+            double acc = 0.0;
+            for (int i = 0; i <= N; ++i) {
+                const double r = exp(u0 + i * h);
+                const double s = psi(r);
+                const double f = (p - P(r)) * exp(-r / rho0) / (s * s) * r;
+                acc += f * (i == 0 || i == N ? 1.0 : (i & 1 ? 4.0 : 2.0));
+            }
+            return acc * h / 3.0;
+        };
+        double lo = P(s_hi) > 0.0 ? P(s_hi) : 0.0, hi = P(s_lo);
+        const double eps = 1e-12 * (hi - lo);
+        const double p = bisect(area, lo + eps, hi - eps);
+        branches(p, rv, rl);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lbm_equal_area(double G, int32_t psi, double rho0, double *rho_l, double *rho_v) {
+    if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
+    if (psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", psi);
+    if (!(rho0 > 0.0) || !isfinite(rho0)) return fail(LBM_ERR_INVALID_ARG, "rho0 must be > 0");
+    if (!(G < -4.0 / rho0) || !isfinite(G))
+        return fail(LBM_ERR_INVALID_ARG, "no liquid-vapour coexistence for G = %g (needs G < %g)", G, -4.0 / rho0);
+    EqualArea{G, rho0}.solve(rho_l, rho_v);
+    return LBM_OK;
+}
+
 int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
     if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
     if (psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", psi);
@@ -443,18 +514,47 @@ int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_
     double *d = nullptr;
     hipError_t e = hipMalloc(&d, sizeof(double) * (Q * n + 4));
     if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
-    double best = INFINITY, bl = 0, bv = 0;
-    int st = LBM_OK;
-    for (int k = 0; k < max_chunks; ++k) {
-        double out[4];
-        e = launch_coexistence_chunk(d, n, G, tau, rho0, chunk, k == 0, d + Q * n, nullptr);
-        if (e == hipSuccess) e = hipMemcpy(out, d + Q * n, sizeof(out), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
-            st = fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
-            break;
+    double start_l, start_v;
+    EqualArea{G, rho0}.solve(&start_l, &start_v);
+    // Relaxation stages for tau < 1: tau = 1, then lowered by 0.05 down to
+    // (excluding) the target, each until the chunk residual is below 1e-8 or
+    // 100 chunks.  Then the target tau with the full stopping rule.
+    std::vector<double> stages;
+    if (tau < 1.0)
+        for (int k = 0;; ++k) {
+            const double t = 1.0 - 0.05 * k;
+            if (!(t > tau + 1e-12)) break;
+            stages.push_back(t);
         }
+    bool first = true;
+    double out[4];
+    auto run_chunk = [&](double t) -> hipError_t {
+        hipError_t err = launch_coexistence_chunk(d, n, G, t, rho0, start_l, start_v, chunk, first ? 1 : 0,
+                                                  d + Q * n, nullptr);
+        first = false;
+        if (err == hipSuccess) err = hipMemcpy(out, d + Q * n, sizeof(out), hipMemcpyDeviceToHost);
+        return err;
+    };
+    int st = LBM_OK;
+    bool diverged = false;
+    for (double t : stages) {
+        for (int k = 0; k < 100 && e == hipSuccess; ++k) {
+            e = run_chunk(t);
+            if (e != hipSuccess) break;
+            if (out[3] != 0.0) {
+                diverged = true;
+                break;
+            }
+            if (out[2] < 1e-8) break;
+        }
+        if (e != hipSuccess || diverged) break;
+    }
+    double best = INFINITY, bl = 0, bv = 0;
+    for (int k = 0; k < max_chunks && e == hipSuccess && !diverged; ++k) {
+        e = run_chunk(tau);
+        if (e != hipSuccess) break;
         if (out[3] != 0.0) {
-            if (!(best < INFINITY)) st = fail(LBM_ERR_DIVERGED, "flat interface diverged for G=%g tau=%g", G, tau);
+            if (!(best < INFINITY)) diverged = true;
             break;
         }
         const double res = out[2];
@@ -466,6 +566,8 @@ int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_
         if (res < 1e-12 || (best < 1e-8 && res > 100.0 * best)) break;
     }
     (void)hipFree(d);
+    if (e != hipSuccess) st = fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
+    else if (diverged) st = fail(LBM_ERR_DIVERGED, "flat interface diverged for G=%g tau=%g", G, tau);
     if (st != LBM_OK) return st;
     *rho_l = bl;
     *rho_v = bv;
@@ -1053,15 +1155,20 @@ int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs) {
         a.seed = g->seed;
         if (!(a.rho_l > 0) || !(a.rho_v > 0)) {
             st = lbm_coexistence(b->p[i].G, b->p[i].tau, b->p[i].psi, b->p[i].rho0, &a.rho_l, &a.rho_v);
-            if (st != LBM_OK) {
+            if (st == LBM_ERR_DIVERGED) {
+                // The flat interface itself is unstable at this (G, tau): the case
+                // starts frozen, with non-finite densities its diagnostics report.
+                a.rho_l = a.rho_v = NAN;
+            } else if (st != LBM_OK) {
                 const std::string m = g_err;
                 return fail(st, "case %d: %s", i, m.c_str());
             }
         }
     }
     hipError_t e = hipSuccess;
-    std::vector<int32_t> zeros(b->n, 0);
-    e = hipMemcpyAsync(b->d_frozen, zeros.data(), sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream);
+    std::vector<int32_t> flags(b->n, 0);
+    for (int i = 0; i < b->n; ++i) flags[i] = isnan(args[i].rho_l) ? 1 : 0;  // state in lattice 0
+    e = hipMemcpyAsync(b->d_frozen, flags.data(), sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream);
     for (int i = 0; i < b->n && e == hipSuccess; ++i) e = launch_init_ligament(batch_ref(b, i, 0), args[i], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_init");
@@ -1151,6 +1258,63 @@ int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l) {
     b->tile_index = find_tile(l->tile_x, l->tile_y);
     hipError_t e = batch_upload(b);
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_set_launch");
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *best, double *best_mlups) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
+    if (steps_per_candidate < 1) return fail(LBM_ERR_INVALID_ARG, "steps_per_candidate must be >= 1");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int zcs[] = {4, 8, 16, 32, 64, 128};
+    double best_t = INFINITY;
+    const lbm_launch orig = b->launch;
+    lbm_launch bl = orig;
+    double nodes = 0;
+    for (int i = 0; i < b->n; ++i) nodes += double(b->p[i].nx) * b->p[i].ny * b->p[i].nz;
+    for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
+        lbm_launch l;
+        tile_shape(ti, &l.tile_x, &l.tile_y);
+        for (int zc : zcs) {
+            l.zchunk = zc;
+            b->launch = l;
+            b->tile_index = ti;
+            e = batch_upload(b);
+            if (e != hipSuccess) {
+                if (e == hipErrorInvalidValue) e = hipSuccess;  // more items than the table holds
+                continue;
+            }
+            // launches from the current lattice into the spare one: state unchanged
+            e = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
+                                  b->parity, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
+                e = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
+                                      b->parity, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            const double t = ms / steps_per_candidate;
+            if (t < best_t) {
+                best_t = t;
+                bl = l;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->launch = bl;
+    b->tile_index = find_tile(bl.tile_x, bl.tile_y);
+    if (e == hipSuccess) e = batch_upload(b);
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_autotune");
+    batch_release_graph(b);
+    if (best) *best = bl;
+    if (best_mlups) *best_mlups = nodes / (best_t * 1e-3) / 1e6;
     return LBM_OK;
 }
 

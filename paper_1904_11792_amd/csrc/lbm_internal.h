@@ -91,10 +91,12 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long lo
                            hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Flat-interface coexistence run: `chunk` steps on the 1 x 1 x n slab held in
-// `state` ([19][n] doubles); init != 0 first writes the start profile.
+// `state` ([19][n] doubles); init != 0 first writes the start profile
+// (liquid hi on [n/4, 3n/4), vapour lo elsewhere, tanh of width 4).
 // out[0] = rho(n/2), out[1] = rho(0), out[2] = max |rho - rho_before| over
 // the chunk, out[3] = 1 if a non-finite density appeared.
 hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    int chunk, int init, double *out, hipStream_t s);
+                                    double hi, double lo, int chunk, int init, double *out,
+                                    hipStream_t s);
 
 }  // namespace lbm

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_1904_11792_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_1904_11792_amd/build.py` "
         "(the HIP library is the only implementation)")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -80,6 +80,7 @@ _SIGS = {
     "lbm_create": (ctypes.c_int, [_P(lbm_params), _vp, _sz, _vp, _P(_vp)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_coexistence": (ctypes.c_int, [_d, _d, _i32, _d, _P(_d), _P(_d)]),
+    "lbm_equal_area": (ctypes.c_int, [_d, _i32, _d, _P(_d), _P(_d)]),
     "lbm_init_ligament": (ctypes.c_int, [_vp, _P(lbm_ligament)]),
     "lbm_step": (ctypes.c_int, [_vp, _i64]),
     "lbm_get_fields": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _i32]),
@@ -105,6 +106,7 @@ _SIGS = {
     "lbm_batch_get_fields": (ctypes.c_int, [_vp, _i32, _u32, _vp, _vp, _vp, _vp, _i32]),
     "lbm_batch_set_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_batch_set_graph_chunk": (ctypes.c_int, [_vp, _i32]),
+    "lbm_batch_autotune": (ctypes.c_int, [_vp, _i32, _P(lbm_launch), _P(_d)]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -153,6 +155,12 @@ def lbm_destroy(ctx) -> None:
 def lbm_coexistence(G: float, tau: float, psi: int = LBM_PSI_EXP, rho0: float = 1.0):
     rl, rv = _d(), _d()
     _check(_lib.lbm_coexistence(G, tau, psi, rho0, ctypes.byref(rl), ctypes.byref(rv)))
+    return rl.value, rv.value
+
+
+def lbm_equal_area(G: float, psi: int = LBM_PSI_EXP, rho0: float = 1.0):
+    rl, rv = _d(), _d()
+    _check(_lib.lbm_equal_area(G, psi, rho0, ctypes.byref(rl), ctypes.byref(rv)))
     return rl.value, rv.value
 
 
@@ -424,3 +432,9 @@ class Batch:
 
     def set_graph_chunk(self, chunk_steps: int) -> None:
         _check(_lib.lbm_batch_set_graph_chunk(self.handle, chunk_steps))
+
+    def autotune(self, steps_per_candidate: int = 3):
+        l = lbm_launch()
+        m = _d()
+        _check(_lib.lbm_batch_autotune(self.handle, steps_per_candidate, ctypes.byref(l), ctypes.byref(m)))
+        return (l.tile_x, l.tile_y, l.zchunk), m.value

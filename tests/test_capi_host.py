@@ -102,3 +102,15 @@ def test_batch_validation(lbm):
     assert "storage" in lbm.lbm_last_error()
     ok = (lbm.lbm_params * 1)(ps[0])
     assert lbm._lib.lbm_batch_workspace_bytes(1, ok) > 2 * 19 * 24 * 24 * 40 * 4
+
+
+@pytest.mark.parametrize("G", [-4.2, -5.0, -5.3, -5.5, -6.0, -7.0])
+def test_equal_area_construction_matches_oracle(lbm, oracle_mod, G):
+    """Host-side construction of the library (bisection + Simpson) against the
+    oracle's (scipy brentq + quad), written independently."""
+    rl, rv = lbm.lbm_equal_area(G)
+    ol, ov = oracle_mod.equal_area(G)
+    assert rl == pytest.approx(ol, rel=1e-12)
+    assert rv == pytest.approx(ov, rel=1e-12)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_equal_area(-3.9)

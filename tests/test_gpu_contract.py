@@ -1,0 +1,169 @@
+"""GPU-side contract of the C ABI: edge cases, error paths forced from the
+host, autotuner, diagnostics ring wrap, and parity at the full benchmark size
+in the benchmark's own launch configuration."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_11792_amd import lbm as mod
+
+    return mod
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 1), (1, 3, 2), (3, 1, 5)])
+def test_degenerate_grids_match_oracle(lbm, oracle_mod, shape):
+    """Grids where neighbours wrap onto the node itself or its only partner."""
+    nx, ny, nz = shape
+    f = workloads.random_populations((nz, ny, nx), seed=sum(shape), base=1.1, spread=0.4)
+    lat = lbm.Lattice(nx, ny, nz, 0.8, -5.5, storage="f64")
+    lat.set_populations(f)
+    lat.step(25)
+    ref = oracle_mod.run(f, 25, 0.8, -5.5)
+    assert _relerr(lat.populations().cpu().numpy(), ref) < 1e-12
+
+
+def test_zero_steps_and_step_counter(lbm):
+    f = workloads.random_populations((4, 4, 4), seed=1)
+    lat = lbm.Lattice(4, 4, 4, 0.9, -5.0, storage="f32")
+    lat.set_populations(f)
+    before = lat.populations().cpu().numpy()
+    lat.step(0)
+    assert lat.step_count == 0
+    assert np.array_equal(lat.populations().cpu().numpy(), before)
+    lat.step(7)
+    assert lat.step_count == 7
+
+
+def test_uninitialised_and_bad_arguments(lbm):
+    lat = lbm.Lattice(8, 8, 8, 0.9, -5.0, storage="f32")
+    with pytest.raises(lbm.LbmError) as e:
+        lat.step(1)
+    assert e.value.status == lbm.LBM_ERR_STATE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_step(lat.ctx, -1)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    with pytest.raises(lbm.LbmError) as e:
+        lat.set_launch(48, 8, 16)
+    assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
+    with pytest.raises(lbm.LbmError):
+        lat.set_axis(3)
+    with pytest.raises(lbm.LbmError):
+        lat.init_ligament(R0=-1.0, amp_rel=0.1, wavelength=8.0, rho_l=2.0, rho_v=0.1)
+    with pytest.raises(lbm.LbmError):
+        lat.set_graph_chunk(3)
+
+
+def test_divergence_reported_not_raised(lbm):
+    """A non-finite population (forced from the host) is reported by the
+    diagnostics with LBM_ERR_DIVERGED; the step itself stays asynchronous."""
+    f = workloads.random_populations((6, 6, 6), seed=2)
+    f[3, 2, 2, 2] = np.nan
+    lat = lbm.Lattice(6, 6, 6, 0.9, -5.0, storage="f32")
+    lat.set_populations(f)
+    lat.step(2)
+    d = lat.diagnostics()
+    assert d["diverged"] and d["nonfinite"] > 0
+    g = workloads.random_populations((6, 6, 6), seed=2)
+    g[0, 1, 1, 1] = -5.0  # negative density at one node
+    lat.set_populations(g)
+    d = lat.diagnostics()
+    assert d["diverged"] and d["nonfinite"] == 1
+
+
+def test_batch_freezes_diverged_case(lbm):
+    import torch
+
+    cases = workloads.batch64(seed=11, count=3)
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
+                               rho_l=2.3, rho_v=0.1, seed=c.seed) for c in cases]
+    # case 1 gets an unstable relaxation time close to 1/2 and a strong attraction
+    params[1] = lbm.make_params(cases[1].nx, cases[1].ny, cases[1].nz, 0.5001, -7.5, storage="f32")
+    b = lbm.Batch(params)
+    b.init(specs)
+    b.step(1000)  # the divergence check runs every 1000 steps
+    d = b.diagnostics()
+    assert d[1]["nonfinite"] > 0
+    assert d[0]["nonfinite"] == 0 and d[2]["nonfinite"] == 0
+    frozen_state = b.fields(1, rho=False, pop=True)["pop"].cpu().numpy()
+    b.step(10)
+    assert np.array_equal(b.fields(1, rho=False, pop=True)["pop"].cpu().numpy(), frozen_state,
+                          equal_nan=True)
+    torch.cuda.synchronize()
+
+
+def test_diag_ring_keeps_last_records(lbm):
+    lat = lbm.Lattice(8, 8, 8, 0.9, -5.0, storage="f32")
+    lat.set_populations(workloads.random_populations((8, 8, 8), seed=4))
+    for _ in range(lbm.LBM_DIAG_RING + 10):
+        lat.record_diag()
+    h = lat.read_diag_history()
+    assert len(h) == lbm.LBM_DIAG_RING
+
+
+def test_autotune_keeps_state_and_caches(lbm, tmp_path):
+    os.environ["LBM_TUNE_CACHE"] = str(tmp_path / "tune.json")
+    try:
+        lat = lbm.Lattice(40, 36, 48, 0.9, -5.5, storage="f32")
+        lat.init_ligament(R0=8.0, amp_rel=0.1, wavelength=48.0, rho_l=2.3, rho_v=0.1, noise_amp=1e-3, seed=3)
+        before = lat.populations().cpu().numpy()
+        (tx, ty, zc), mlups = lat.autotune(2)
+        assert (tx, ty) in lbm.lbm_list_tiles() and zc >= 1 and mlups > 0
+        assert np.array_equal(lat.populations().cpu().numpy(), before)
+        assert lat.get_launch() == (tx, ty, zc)
+        cache = json.load(open(tmp_path / "tune.json"))
+        assert any(v == [tx, ty, zc] for v in cache.values())
+        again = lbm.Lattice(40, 36, 48, 0.9, -5.5, storage="f32")
+        assert again.get_launch() == (tx, ty, zc)
+    finally:
+        del os.environ["LBM_TUNE_CACHE"]
+
+
+def test_full_size_benchmark_grid_parity(lbm, oracle_mod):
+    """256 x 256 x 1024 FP32 in the benchmark's launch configuration: density of
+    every node after 3 steps against the FP64 oracle, populations at sampled
+    nodes, and FP64 mass over 200 steps."""
+    import torch
+
+    s = workloads.LARGE_FP32
+    rho_l, rho_v = 2.2726347743066544, 0.07423656758557648
+    spec = dict(R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength, rho_l=rho_l, rho_v=rho_v,
+                noise_amp=s.noise_amp, seed=s.seed)
+    lat = lbm.Lattice(s.nx, s.ny, s.nz, s.tau, s.G, storage="f32", rho_ref=rho_v)
+    lat.init_ligament(**spec)
+    m0 = lat.diagnostics()["mass"]
+    lat.step(3)
+    rho = lat.fields()["rho"].cpu().numpy()
+    pop = lat.populations()
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, s.n, 20000)
+    pop_s = pop.reshape(19, -1)[:, torch.as_tensor(idx, device=pop.device)].cpu().numpy()
+    del pop
+    f = oracle_mod.init_ligament(s.nx, s.ny, s.nz, **spec)
+    f = oracle_mod.run(f, 3, s.tau, s.G)
+    ref_pop = f.reshape(19, -1)[:, idx]
+    ref_rho = f.sum(axis=0)
+    del f
+    assert _relerr(rho, ref_rho) < 1e-5
+    assert _relerr(pop_s, ref_pop) < 1e-5
+    lat.step(197)
+    d = lat.diagnostics()
+    assert d["nonfinite"] == 0
+    assert abs(d["mass"] - m0) / m0 < 1e-6

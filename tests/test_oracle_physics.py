@@ -53,17 +53,24 @@ def sc94_construction(G):
     return rl, rv
 
 
-def test_sc94_construction_reference_values():
-    """The construction itself, at G = -5.5 (values from the survey-time probe)."""
+def test_sc94_construction_reference_values(oracle_mod):
+    """The construction itself, at G = -5.5 (values from the survey-time probe),
+    and the oracle's bracketing implementation against this test's fsolve one."""
     rl, rv = sc94_construction(-5.5)
     assert rl == pytest.approx(2.30752, abs=2e-5)
     assert rv == pytest.approx(0.10481, abs=2e-5)
+    for G in (-4.5, -5.3, -6.0):
+        a = sc94_construction(G)
+        b = oracle_mod.equal_area(G)
+        assert a[0] == pytest.approx(b[0], rel=1e-10) and a[1] == pytest.approx(b[1], rel=1e-9)
 
 
 @pytest.mark.parametrize("G", [-5.5, -6.0])
 def test_flat_interface_matches_equal_area_at_tau_one(oracle_mod, G):
+    """Started away from the construction (2.1 / 0.1), the flat interface
+    relaxes to within 0.1% / 1% of it."""
     rl_c, rv_c = sc94_construction(G)
-    co = oracle_mod.coexistence(G, 1.0)
+    co = oracle_mod.coexistence(G, 1.0, rho_hi=2.1, rho_lo=0.1)
     assert co.residual < 1e-8
     assert co.rho_l == pytest.approx(rl_c, rel=1e-3)
     assert co.rho_v == pytest.approx(rv_c, rel=1e-2)
