@@ -216,7 +216,9 @@ int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 /*
  * Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
  * nodes (one thread each) marching zchunk planes along z.  Supported tiles:
- * see lbm_list_tiles.  zchunk >= 1.
+ * see lbm_list_tiles.  tile_x = tile_y = 0 selects a tile shaped at run time
+ * for the grid: width min(nx, 128) (whole rows up to 128 nodes), height
+ * balanced over ny with at most 512 nodes and 64 rows.  zchunk >= 1.
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

@@ -166,23 +166,35 @@ void cache_store(const std::string &key, const lbm_launch &l) {
     rename(tmp.c_str(), path);
 }
 
+// Tile width/height of a launch on an nx x ny cross-section (tile_x = 0
+// selects the run-time shaped tile).
+void tile_dims(const lbm_launch &l, int nx, int ny, int *tw, int *th) {
+    if (l.tile_x == 0)
+        dynamic_tile(nx, ny, tw, th);
+    else {
+        *tw = l.tile_x;
+        *th = l.tile_y;
+    }
+}
+
 // Default launch shape: the widest compiled tile that fits the x extent
-// (whole rows of the row-interleaved layout stream best), and about one
-// workgroup per compute unit (256) by choosing the z chunk.
+// (whole rows of the row-interleaved layout stream best; below 128 nodes the
+// run-time shaped full-row tile), and about one workgroup per compute unit
+// (256) by choosing the z chunk.
 lbm_launch default_launch(const lbm_params *p) {
     lbm_launch l;
-    if (p->nx >= 256) {
+    if (p->nx >= 256 && p->storage != LBM_F64) {
         l.tile_x = 256; l.tile_y = 4;
+    } else if (p->nx >= 128 && p->storage == LBM_F64) {
+        l.tile_x = 128; l.tile_y = 4;  // 512 threads: the FP64 kernel needs > 128 VGPRs
     } else if (p->nx >= 128) {
         l.tile_x = 128; l.tile_y = 8;
-    } else if (p->nx >= 64) {
-        l.tile_x = 64; l.tile_y = 16;
-    } else if (p->nx >= 32) {
-        l.tile_x = 32; l.tile_y = 16;
     } else {
-        l.tile_x = 16; l.tile_y = 16;
+        l.tile_x = 0; l.tile_y = 0;  // full-row tile shaped at run time
     }
-    const int64_t tiles = int64_t((p->nx + l.tile_x - 1) / l.tile_x) * ((p->ny + l.tile_y - 1) / l.tile_y);
+    int tw, th;
+    tile_dims(l, p->nx, p->ny, &tw, &th);
+    const int64_t tiles = int64_t((p->nx + tw - 1) / tw) * ((p->ny + th - 1) / th);
     int64_t chunks = (256 + tiles - 1) / tiles;
     int64_t zc = (p->nz + chunks - 1) / chunks;
     if (zc < 4) zc = 4;
@@ -262,11 +274,11 @@ StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
     A.nx = c->p.nx;
     A.ny = c->p.ny;
     A.nz = c->p.nz;
-    A.tiles_x = (c->p.nx + l.tile_x - 1) / l.tile_x;
-    A.tiles_y = (c->p.ny + l.tile_y - 1) / l.tile_y;
+    tile_dims(l, c->p.nx, c->p.ny, &A.tile_w, &A.tile_h);
+    A.tiles_x = (c->p.nx + A.tile_w - 1) / A.tile_w;
+    A.tiles_y = (c->p.ny + A.tile_h - 1) / A.tile_h;
     A.zchunk = l.zchunk < c->p.nz ? l.zchunk : c->p.nz;
     A.nchunks = (c->p.nz + A.zchunk - 1) / A.zchunk;
-    A.pad_ = 0;
     A.pop_stride = c->lay.S;
     A.row_stride = c->lay.R;
     A.plane_stride = c->lay.P;
@@ -875,6 +887,11 @@ namespace {
 constexpr int kBatchMinZchunk = 4;
 
 int64_t items_for(const lbm_params &p, int tx, int ty, int zc) {
+    lbm_launch l;
+    l.tile_x = tx;
+    l.tile_y = ty;
+    l.zchunk = zc;
+    tile_dims(l, p.nx, p.ny, &tx, &ty);
     const int64_t t = int64_t((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
     const int z = zc < p.nz ? zc : p.nz;
     return t * ((p.nz + z - 1) / z);
@@ -986,11 +1003,11 @@ hipError_t batch_upload(lbm_batch *b) {
         A.nx = b->p[i].nx;
         A.ny = b->p[i].ny;
         A.nz = b->p[i].nz;
-        A.tiles_x = (A.nx + l.tile_x - 1) / l.tile_x;
-        A.tiles_y = (A.ny + l.tile_y - 1) / l.tile_y;
+        tile_dims(l, A.nx, A.ny, &A.tile_w, &A.tile_h);
+        A.tiles_x = (A.nx + A.tile_w - 1) / A.tile_w;
+        A.tiles_y = (A.ny + A.tile_h - 1) / A.tile_h;
         A.zchunk = l.zchunk < A.nz ? l.zchunk : A.nz;
         A.nchunks = (A.nz + A.zchunk - 1) / A.zchunk;
-        A.pad_ = 0;
         A.pop_stride = b->lay[i].S;
         A.row_stride = b->lay[i].R;
         A.plane_stride = b->lay[i].P;
@@ -1060,11 +1077,11 @@ hipError_t batch_build_graph(lbm_batch *b) {
 }
 
 lbm_launch batch_default_launch(int n, const lbm_params *p) {
+    (void)n;
+    (void)p;
     lbm_launch l;
-    int maxnx = 1;
-    for (int i = 0; i < n; ++i) maxnx = p[i].nx > maxnx ? p[i].nx : maxnx;
-    l.tile_x = maxnx >= 64 ? 64 : 32;
-    l.tile_y = 8;
+    l.tile_x = 0;  // each case gets its own full-row tile shape
+    l.tile_y = 0;
     l.zchunk = 16;
     return l;
 }

@@ -15,7 +15,7 @@ struct StepArgs {
     void *dst;
     int nx, ny, nz;
     int tiles_x, tiles_y, zchunk, nchunks;
-    int pad_;
+    int tile_w, tile_h;  // tile shape (used by the run-time shaped kernel)
     // element offset of population a at node (x, y, z):
     //   a * pop_stride + z * plane_stride + y * row_stride + x
     // (the node part, z * plane_stride + y * row_stride + x, fits in 32 bits)
@@ -65,6 +65,9 @@ struct LigamentArgs {
 };
 
 // lbm_step.hip
+// Run-time shaped tile for a grid: width min(nx, 128), height balanced over
+// ny with at most 512 nodes and 64 rows per tile.
+void dynamic_tile(int nx, int ny, int *tw, int *th);
 int num_tiles();
 void tile_shape(int i, int *tx, int *ty);
 int find_tile(int tx, int ty);

@@ -26,16 +26,26 @@
 
 namespace lbm {
 
-template <int ST, int TX, int TY>
+// Tile shape: compile-time (TXS x TYS) or, with TXS = TYS = 0, chosen per
+// grid at run time (A.tile_w x A.tile_h, at most kDynThreads nodes, tile_w at
+// most 128, tile_h at most 64: then (tile_w + 2)(tile_h + 2) <= kDynWin and
+// the ring has at most kDynThreads nodes).
+constexpr int kDynThreads = 512;
+constexpr int kDynWin = 900;
+
+template <int ST, int TXS, int TYS>
 __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk) {
     using Tr = Storage<ST>;
     using T = typename Tr::T;
     using C = typename Tr::C;
-    constexpr int PX = TX + 2;
-    constexpr int PY = TY + 2;
-    constexpr int RING = 2 * PX + 2 * TY;
-    static_assert(RING <= TX * TY, "ring must fit the thread count");
-    __shared__ C win[4][PY][PX];
+    static_assert(TXS == 0 || 2 * (TXS + 2) + 2 * TYS <= TXS * TYS, "ring must fit the thread count");
+    const int TX = TXS ? TXS : A.tile_w;
+    const int TY = TYS ? TYS : A.tile_h;
+    const int PX = TX + 2;
+    const int RING = 2 * PX + 2 * TY;
+    constexpr int WIN = TXS ? (TXS + 2) * (TYS + 2) : kDynWin;
+    __shared__ C win[4 * WIN];  // psi window: 4 planes of (TY + 2) x (TX + 2)
+    auto W = [&](int s, int yy, int xx) -> C & { return win[s * WIN + yy * PX + xx]; };
 
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const int plane = A.plane_stride, rowst = A.row_stride;
@@ -53,8 +63,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int kend = min(A.zchunk, nz - z0);
 
     const int t = threadIdx.x;
-    const int lx = t % TX, ly = t / TX;
-    const bool active = (x0 + lx < nx) && (y0 + ly < ny);
+    // threads beyond a run-time tile only take part in the barriers
+    const bool inside = TXS ? true : t < TX * TY;
+    const int lx = inside ? t % TX : 0, ly = inside ? t / TX : 0;
+    const bool active = inside && (x0 + lx < nx) && (y0 + ly < ny);
     // Source columns/rows of the pull: index (1 - c) selects x - c.
     const int gx = wrapi(x0 + lx, nx), gy = wrapi(y0 + ly, ny);
     const int X[3] = {wrapi(gx - 1, nx), gx, wrapi(gx + 1, nx)};
@@ -88,12 +100,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     };
     // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
     auto load_plane = [&](int zc, int s, C(&f)[Q]) {
-        gather(zc, X, Y, f);
-        win[s][ly + 1][lx + 1] = pseudo_potential(density(f), rho0, inv_rho0);
+        if (inside) {
+            gather(zc, X, Y, f);
+            W(s, ly + 1, lx + 1) = pseudo_potential(density(f), rho0, inv_rho0);
+        }
         if (ring) {
             C g[Q];
             gather(zc, RX, RY, g);
-            win[s][ry + 1][rx + 1] = pseudo_potential(density(g), rho0, inv_rho0);
+            W(s, ry + 1, rx + 1) = pseudo_potential(density(g), rho0, inv_rho0);
         }
     };
 
@@ -102,10 +116,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         const int sm = (k + 3) & 3, s0 = k & 3, sp = (k + 1) & 3;
         auto P = [&](int dx, int dy, int dz) -> C {
             const int s = dz < 0 ? sm : (dz > 0 ? sp : s0);
-            return win[s][ly + 1 + dy][lx + 1 + dx];
+            return W(s, ly + 1 + dy, lx + 1 + dx);
         };
         C Fx, Fy, Fz;
-        sc_force<C>(win[s0][ly + 1][lx + 1], G, P, Fx, Fy, Fz);
+        sc_force<C>(W(s0, ly + 1, lx + 1), G, P, Fx, Fy, Fz);
         collide<C>(f, Fx, Fy, Fz, tau, omega);
         const int o = zc * plane + Y[1] + X[1];
 #pragma unroll
@@ -127,7 +141,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 }
 
 template <int ST, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_step(StepArgs A) {
+__global__ __launch_bounds__(TX ? TX * TY : kDynThreads) void k_step(StepArgs A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
@@ -138,7 +152,7 @@ __global__ __launch_bounds__(TX *TY) void k_step(StepArgs A) {
 // (case, tile, chunk) triples; case parameters and lattice pointers come from
 // a device table; frozen cases are skipped.
 template <int ST, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_step_batch(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(TX ? TX * TY : kDynThreads) void k_step_batch(const BatchCase *__restrict__ cases,
                                                        const int4 *__restrict__ items,
                                                        const int32_t *__restrict__ frozen,
                                                        int parity) {
@@ -169,11 +183,21 @@ struct TileEntry {
       (const void *)k_step_batch<kF16S, TXV, TYV>,                                          \
       (const void *)k_step_batch<kBF16S, TXV, TYV>}}
 
+// Entry (0, 0) is the run-time shaped tile (kDynThreads threads).
 static const TileEntry kTiles[] = {
-    LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
+    LBM_TILE(0, 0), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
     LBM_TILE(64, 4), LBM_TILE(32, 16), LBM_TILE(32, 8), LBM_TILE(16, 16),
 };
 #undef LBM_TILE
+
+void dynamic_tile(int nx, int ny, int *tw, int *th) {
+    const int w = nx < 128 ? nx : 128;
+    int hmax = kDynThreads / w;
+    if (hmax > 64) hmax = 64;
+    const int ntile_y = (ny + hmax - 1) / hmax;
+    *tw = w;
+    *th = (ny + ntile_y - 1) / ntile_y;
+}
 
 int num_tiles() { return int(sizeof(kTiles) / sizeof(kTiles[0])); }
 void tile_shape(int i, int *tx, int *ty) {
@@ -191,7 +215,8 @@ hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream
     const int nblk = A.tiles_x * A.tiles_y * A.nchunks;
     StepArgs args = A;
     void *kargs[] = {&args};
-    return hipLaunchKernel(e.fn[storage], dim3(nblk), dim3(e.tx * e.ty), kargs, 0, s);
+    const int threads = e.tx ? e.tx * e.ty : kDynThreads;
+    return hipLaunchKernel(e.fn[storage], dim3(nblk), dim3(threads), kargs, 0, s);
 }
 
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
@@ -199,7 +224,8 @@ hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases
                              hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
     void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity};
-    return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(e.tx * e.ty), kargs, 0, s);
+    const int threads = e.tx ? e.tx * e.ty : kDynThreads;
+    return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(threads), kargs, 0, s);
 }
 
 }  // namespace lbm

@@ -94,7 +94,10 @@ def test_batch_freezes_diverged_case(lbm):
     params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
     specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
                                rho_l=2.3, rho_v=0.1, seed=c.seed) for c in cases]
-    # case 1 gets an unstable relaxation time close to 1/2 and a strong attraction
+    # cases 0 and 2 get a stable (tau, G); case 1 an unstable relaxation time
+    # close to 1/2 with a strong attraction
+    for i in (0, 2):
+        params[i] = lbm.make_params(cases[i].nx, cases[i].ny, cases[i].nz, 1.0, -5.5, storage="f32")
     params[1] = lbm.make_params(cases[1].nx, cases[1].ny, cases[1].nz, 0.5001, -7.5, storage="f32")
     b = lbm.Batch(params)
     b.init(specs)
@@ -161,8 +164,13 @@ def test_full_size_benchmark_grid_parity(lbm, oracle_mod):
     ref_pop = f.reshape(19, -1)[:, idx]
     ref_rho = f.sum(axis=0)
     del f
-    assert _relerr(rho, ref_rho) < 1e-5
-    assert _relerr(pop_s, ref_pop) < 1e-5
+    err_rho = _relerr(rho, ref_rho)
+    # populations: error relative to the density of their node (small moving
+    # populations carry the absolute FP32 error of the whole node)
+    err_pop = float(np.max(np.abs(pop_s - ref_pop) / ref_rho.reshape(-1)[idx]))
+    print(f"full size FP32 after 3 steps: density {err_rho:.2e}, populations/rho {err_pop:.2e}")
+    assert err_rho < 1e-5
+    assert err_pop < 1e-5
     lat.step(197)
     d = lat.diagnostics()
     assert d["nonfinite"] == 0

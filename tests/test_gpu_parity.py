@@ -253,8 +253,8 @@ def test_batch_case_equals_single_run(lbm):
     b.step(30)
     for i, c in enumerate(cases):
         single = lbm.Lattice(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32")
-        tx, ty, zc = b_launch = (32 if max(p.nx for p in params) < 64 else 64, 8, 16)
-        single.set_launch(tx, ty, zc)
+        b_launch = (0, 0, 16)  # the batch's default: run-time shaped full-row tiles
+        single.set_launch(*b_launch)
         single.init_ligament(R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength, rho_l=RHO_L,
                              rho_v=RHO_V, seed=c.seed)
         single.step(30)
