@@ -243,7 +243,8 @@ def sweep(lat, spec, stream, storage):
             e1.synchronize()
             row.append(e0.elapsed_time(e1) / 10)
         best = min(row)
-        print(f"| {tx}x{ty} | " + " | ".join(f"{v:.3f}" for v in row) +
+        name = f"{tx}x{ty}" if tx else f"run-time, {ty} threads"
+        print(f"| {name} | " + " | ".join(f"{v:.3f}" for v in row) +
               f" | {bpn * spec.n / best / 1e6:.0f} |", flush=True)
 
 

@@ -216,9 +216,12 @@ int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 /*
  * Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
  * nodes (one thread each) marching zchunk planes along z.  Supported tiles:
- * see lbm_list_tiles.  tile_x = tile_y = 0 selects a tile shaped at run time
- * for the grid: width min(nx, 128) (whole rows up to 128 nodes), height
- * balanced over ny with at most 512 nodes and 64 rows.  zchunk >= 1.
+ * see lbm_list_tiles.  tile_x = 0 selects a tile shaped at run time for the
+ * grid, for a workgroup of tile_y threads (512 or 1024): width min(nx, 128)
+ * for 512 threads or min(nx, 256) for 1024 (whole rows up to that width),
+ * height balanced over ny with at most tile_y nodes and 64 rows.
+ * zchunk >= 1.  The FP64 kernel is slow with 1024 threads (its registers do
+ * not fit), the other storages run fastest there on grids of nx >= 128.
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

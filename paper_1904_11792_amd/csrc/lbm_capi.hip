@@ -170,28 +170,22 @@ void cache_store(const std::string &key, const lbm_launch &l) {
 // selects the run-time shaped tile).
 void tile_dims(const lbm_launch &l, int nx, int ny, int *tw, int *th) {
     if (l.tile_x == 0)
-        dynamic_tile(nx, ny, tw, th);
+        dynamic_tile(l.tile_y, nx, ny, tw, th);
     else {
         *tw = l.tile_x;
         *th = l.tile_y;
     }
 }
 
-// Default launch shape: the widest compiled tile that fits the x extent
-// (whole rows of the row-interleaved layout stream best; below 128 nodes the
-// run-time shaped full-row tile), and about one workgroup per compute unit
-// (256) by choosing the z chunk.
+// Default launch shape: the run-time shaped tile, which spans whole rows up to
+// 256 nodes (whole rows of the row-interleaved layout stream best), and about
+// one workgroup per compute unit (256) by choosing the z chunk.
 lbm_launch default_launch(const lbm_params *p) {
     lbm_launch l;
-    if (p->nx >= 256 && p->storage != LBM_F64) {
-        l.tile_x = 256; l.tile_y = 4;
-    } else if (p->nx >= 128 && p->storage == LBM_F64) {
-        l.tile_x = 128; l.tile_y = 4;  // 512 threads: the FP64 kernel needs > 128 VGPRs
-    } else if (p->nx >= 128) {
-        l.tile_x = 128; l.tile_y = 8;
-    } else {
-        l.tile_x = 0; l.tile_y = 0;  // full-row tile shaped at run time
-    }
+    l.tile_x = 0;  // full-row tile shaped at run time
+    // 1024 threads for wide grids; FP64 keeps 512 (its kernel needs more than
+    // the 128 VGPRs a 1024-thread workgroup allows)
+    l.tile_y = (p->nx >= 128 && p->storage != LBM_F64) ? 1024 : 512;
     int tw, th;
     tile_dims(l, p->nx, p->ny, &tw, &th);
     const int64_t tiles = int64_t((p->nx + tw - 1) / tw) * ((p->ny + th - 1) / th);
@@ -1081,7 +1075,7 @@ lbm_launch batch_default_launch(int n, const lbm_params *p) {
     (void)p;
     lbm_launch l;
     l.tile_x = 0;  // each case gets its own full-row tile shape
-    l.tile_y = 0;
+    l.tile_y = 512;
     l.zchunk = 16;
     return l;
 }

@@ -65,9 +65,10 @@ struct LigamentArgs {
 };
 
 // lbm_step.hip
-// Run-time shaped tile for a grid: width min(nx, 128), height balanced over
-// ny with at most 512 nodes and 64 rows per tile.
-void dynamic_tile(int nx, int ny, int *tw, int *th);
+// Run-time shaped tile of a `threads`-thread workgroup (512 or 1024) for a
+// grid: width min(nx, 128 or 256), height balanced over ny with at most
+// `threads` nodes and 64 rows per tile.
+void dynamic_tile(int threads, int nx, int ny, int *tw, int *th);
 int num_tiles();
 void tile_shape(int i, int *tx, int *ty);
 int find_tile(int tx, int ty);

@@ -26,12 +26,13 @@
 
 namespace lbm {
 
-// Tile shape: compile-time (TXS x TYS) or, with TXS = TYS = 0, chosen per
-// grid at run time (A.tile_w x A.tile_h, at most kDynThreads nodes, tile_w at
-// most 128, tile_h at most 64: then (tile_w + 2)(tile_h + 2) <= kDynWin and
-// the ring has at most kDynThreads nodes).
-constexpr int kDynThreads = 512;
-constexpr int kDynWin = 900;
+// Tile shape: compile-time (TXS x TYS), or with TXS = 0 chosen per grid at
+// run time (A.tile_w x A.tile_h) for a workgroup of TYS threads: tile_w at
+// most 128 (512 threads) or 256 (1024 threads), tile_h at most 64 and
+// tile_w * tile_h at most TYS.  Then (tile_w + 2)(tile_h + 2) is at most
+// 900 (512 threads) or 1548 (1024 threads) and the ring fits the threads.
+__host__ __device__ constexpr int dyn_window(int threads) { return threads == 512 ? 900 : 1600; }
+__host__ __device__ constexpr int dyn_width_cap(int threads) { return threads == 512 ? 128 : 256; }
 
 template <int ST, int TXS, int TYS>
 __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk) {
@@ -39,11 +40,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     using T = typename Tr::T;
     using C = typename Tr::C;
     static_assert(TXS == 0 || 2 * (TXS + 2) + 2 * TYS <= TXS * TYS, "ring must fit the thread count");
+    static_assert(TXS != 0 || TYS == 512 || TYS == 1024, "run-time tiles use 512 or 1024 threads");
     const int TX = TXS ? TXS : A.tile_w;
-    const int TY = TYS ? TYS : A.tile_h;
+    const int TY = TXS ? TYS : A.tile_h;
     const int PX = TX + 2;
     const int RING = 2 * PX + 2 * TY;
-    constexpr int WIN = TXS ? (TXS + 2) * (TYS + 2) : kDynWin;
+    constexpr int WIN = TXS ? (TXS + 2) * (TYS + 2) : dyn_window(TYS);
     __shared__ C win[4 * WIN];  // psi window: 4 planes of (TY + 2) x (TX + 2)
     auto W = [&](int s, int yy, int xx) -> C & { return win[s * WIN + yy * PX + xx]; };
 
@@ -63,8 +65,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int kend = min(A.zchunk, nz - z0);
 
     const int t = threadIdx.x;
-    // threads beyond a run-time tile only take part in the barriers
-    const bool inside = TXS ? true : t < TX * TY;
+    // Threads beyond a run-time tile only take part in the barriers.  The test
+    // uses the run-time tile size for fixed tiles too: as a compile-time
+    // constant it lets the compiler merge the tile and ring gathers, which
+    // made the 16-bit storage kernels up to 1.7x slower on MI355X.
+    const bool inside = t < A.tile_w * A.tile_h;
     const int lx = inside ? t % TX : 0, ly = inside ? t / TX : 0;
     const bool active = inside && (x0 + lx < nx) && (y0 + ly < ny);
     // Source columns/rows of the pull: index (1 - c) selects x - c.
@@ -141,7 +146,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 }
 
 template <int ST, int TX, int TY>
-__global__ __launch_bounds__(TX ? TX * TY : kDynThreads) void k_step(StepArgs A) {
+__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step(StepArgs A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(TX ? TX * TY : kDynThreads) void k_step(StepArgs A)
 // (case, tile, chunk) triples; case parameters and lattice pointers come from
 // a device table; frozen cases are skipped.
 template <int ST, int TX, int TY>
-__global__ __launch_bounds__(TX ? TX * TY : kDynThreads) void k_step_batch(const BatchCase *__restrict__ cases,
+__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_batch(const BatchCase *__restrict__ cases,
                                                        const int4 *__restrict__ items,
                                                        const int32_t *__restrict__ frozen,
                                                        int parity) {
@@ -183,16 +188,17 @@ struct TileEntry {
       (const void *)k_step_batch<kF16S, TXV, TYV>,                                          \
       (const void *)k_step_batch<kBF16S, TXV, TYV>}}
 
-// Entry (0, 0) is the run-time shaped tile (kDynThreads threads).
+// Entries (0, 512) and (0, 1024) are the run-time shaped tiles.
 static const TileEntry kTiles[] = {
-    LBM_TILE(0, 0), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
+    LBM_TILE(0, 512), LBM_TILE(0, 1024), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
     LBM_TILE(64, 4), LBM_TILE(32, 16), LBM_TILE(32, 8), LBM_TILE(16, 16),
 };
 #undef LBM_TILE
 
-void dynamic_tile(int nx, int ny, int *tw, int *th) {
-    const int w = nx < 128 ? nx : 128;
-    int hmax = kDynThreads / w;
+void dynamic_tile(int threads, int nx, int ny, int *tw, int *th) {
+    const int cap = dyn_width_cap(threads);
+    const int w = nx < cap ? nx : cap;
+    int hmax = threads / w;
     if (hmax > 64) hmax = 64;
     const int ntile_y = (ny + hmax - 1) / hmax;
     *tw = w;
@@ -215,7 +221,7 @@ hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream
     const int nblk = A.tiles_x * A.tiles_y * A.nchunks;
     StepArgs args = A;
     void *kargs[] = {&args};
-    const int threads = e.tx ? e.tx * e.ty : kDynThreads;
+    const int threads = e.tx ? e.tx * e.ty : e.ty;
     return hipLaunchKernel(e.fn[storage], dim3(nblk), dim3(threads), kargs, 0, s);
 }
 
@@ -224,7 +230,7 @@ hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases
                              hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
     void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity};
-    const int threads = e.tx ? e.tx * e.ty : kDynThreads;
+    const int threads = e.tx ? e.tx * e.ty : e.ty;
     return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(threads), kargs, 0, s);
 }
 

@@ -35,8 +35,9 @@ def test_version_and_tiles(lbm):
     assert "gfx950" in lbm.lbm_version()
     tiles = lbm.lbm_list_tiles()
     assert (64, 8) in tiles and (32, 8) in tiles
+    assert (0, 512) in tiles and (0, 1024) in tiles  # run-time shaped tiles
     for tx, ty in tiles:
-        assert tx % 16 == 0 and tx * ty <= 1024
+        assert tx % 16 == 0 and (tx * ty if tx else ty) <= 1024
 
 
 def test_workspace_bytes_and_validation(lbm):

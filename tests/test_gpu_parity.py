@@ -243,6 +243,25 @@ def test_shifted_storage_round_trip_is_exact(lbm, storage):
     assert torch.equal(back, pop)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_run_time_tiles_on_wide_grid(lbm, oracle_mod, storage):
+    """Both run-time shaped tiles on a grid wider than either width cap (a
+    ragged last column of tiles) and a z chunk that leaves a ragged tail."""
+    nx, ny, nz = 300, 9, 11
+    spec = dict(R0=3.0, amp_rel=0.1, wavelength=11.0, noise_amp=1e-3, seed=12)
+    f0 = oracle_mod.init_ligament(nx, ny, nz, rho_l=RHO_L, rho_v=RHO_V, axis=0, **spec)
+    ref = oracle_mod.run(f0, 4, 0.9, -5.5)
+    for threads in (512, 1024):
+        lat = lbm.Lattice(nx, ny, nz, 0.9, -5.5, storage=storage)
+        lat.set_launch(0, threads, 4)
+        lat.init_ligament(rho_l=RHO_L, rho_v=RHO_V, axis=0, **spec)
+        lat.step(4)
+        got = lat.populations().cpu().numpy()
+        err = _relerr(got, ref)
+        assert err < (1e-13 if storage == "f64" else 1e-5), (threads, err)
+        lat.close()
+
+
 def test_batch_case_equals_single_run(lbm):
     cases = workloads.batch64(seed=7, count=5)
     params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
@@ -253,7 +272,7 @@ def test_batch_case_equals_single_run(lbm):
     b.step(30)
     for i, c in enumerate(cases):
         single = lbm.Lattice(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32")
-        b_launch = (0, 0, 16)  # the batch's default: run-time shaped full-row tiles
+        b_launch = (0, 512, 16)  # the batch's default: run-time shaped full-row tiles
         single.set_launch(*b_launch)
         single.init_ligament(R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength, rho_l=RHO_L,
                              rho_v=RHO_V, seed=c.seed)
