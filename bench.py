@@ -14,6 +14,12 @@ bounded sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--storage f32|f64|f16s|bf16s]
                   [--form single|batch] [--no-cpu-baseline]
+
+Studies (one JSON line each, not the benchmark line):
+  --form precision    FP16/BF16 shifted storage against FP32/FP64
+  --form convergence  t_b / t_cap against 1/R, FP32 and FP64
+  --form paper        the paper's Table 1 sweep (G = -5.3, Oh = 0.1)
+  --sweep             every compiled tile shape and several z chunks
 """
 from __future__ import annotations
 
@@ -117,7 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
     ap.add_argument("--form", default="single",
-                    choices=["single", "batch", "precision", "convergence"])
+                    choices=["single", "batch", "precision", "convergence", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
@@ -155,6 +161,8 @@ def main():
         return study_precision(args, lbm, workloads, stream)
     if args.form == "convergence":
         return study_convergence(args, lbm, workloads, stream)
+    if args.form == "paper":
+        return study_paper(args, lbm, workloads, stream)
 
     spec = workloads.LARGE_FP32
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
@@ -346,6 +354,46 @@ def study_convergence(args, lbm, workloads, stream):
             print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
     print(json.dumps({"study": "convergence", "G": G, "tau": tau, "rho_l": rho_l, "rho_v": rho_v,
                       "sigma": sigma, "laplace_intercept": icpt, "rows": rows}))
+
+
+def study_paper(args, lbm, workloads, stream):
+    """The paper's sweep (Section 4): G = -5.3, tau from Oh = 0.1, R0 = 7 ... 84.
+    Per radius: flat-interface coexistence and Laplace surface tension on the
+    GPU against Table 1, then the ligament (FP32 storage unless --storage
+    says otherwise) run to break-up: t_b / t_cap against R0, the trend the
+    paper's Fig. 2 shows (its data points are not printed)."""
+    from paper_1904_11792_amd import analysis
+
+    storage = args.storage
+    rows = []
+    for R0, rl_p, rv_p, sg_p in workloads.TABLE1:
+        spec = workloads.paper_table1(R0)
+        rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+        try:
+            sigma, icpt = analysis.laplace_sigma(lbm, spec.G, spec.tau, rho_l, rho_v, width=4.0)
+        except RuntimeError as exc:
+            sigma, icpt = None, str(exc)
+        sg = sigma if sigma is not None else sg_p
+        tcap = analysis.capillary_time(rho_l, R0, sg)
+        print(f"# R0={R0} tau={spec.tau:.4f} rho_l={rho_l:.5f} rho_v={rho_v:.5f} sigma={sigma} "
+              f"grid {spec.nx}x{spec.ny}x{spec.nz}", file=sys.stderr, flush=True)
+        r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps=int(40 * tcap) + 2000,
+                          every=max(1, R0 // 8))
+        r.update({
+            "R0": R0, "grid": [spec.nx, spec.ny, spec.nz], "tau": spec.tau, "storage": storage,
+            "rho_l": rho_l, "rho_v": rho_v, "sigma": sigma, "laplace_intercept": icpt,
+            "paper": {"rho_l": rl_p, "rho_v": rv_p, "sigma": sg_p},
+            "rel_err": {"rho_l": (rho_l - rl_p) / rl_p, "rho_v": (rho_v - rv_p) / rv_p,
+                        "sigma": None if sigma is None else (sigma - sg_p) / sg_p},
+            "Oh": analysis.ohnesorge(spec.tau, rho_l, sg, R0), "t_cap": tcap,
+            "t_b_over_t_cap": None if r["t_b"] is None else r["t_b"] / tcap,
+            "t_b_over_t_cap_paper_scales": None if r["t_b"] is None
+            else r["t_b"] / analysis.capillary_time(rl_p, R0, sg_p),
+            "MLUPS_incl_diag": round(spec.n / r["ms_per_step_incl_diag"] / 1e3, 1)})
+        rows.append(r)
+        print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "paper_table1", "G": workloads.TABLE1_G, "Oh": workloads.TABLE1_OH,
+                      "rows": rows}))
 
 
 def bench_batch(args, lbm, workloads, stream):

@@ -119,11 +119,14 @@ def run_to_breakup(lat, rho_l: float, rho_v: float, max_steps: int, every: int =
 
 
 def laplace_sigma(lbm, G: float, tau: float, rho_l: float, rho_v: float,
-                  radii=(10, 14, 18, 22), N: int = 80, steps: int = 8000, storage="f64"):
+                  radii=(10, 14, 18, 22), N: int = 80, steps: int = 8000, storage="f64",
+                  width: float = 2.0):
     """Surface tension from the Laplace law on quasi-2D cylinders (N x N x 1,
     periodic): fit dp = sigma / R_eq + b over several radii, with
     dp = P(rho_in) - P(rho_out) from the equation of state (Eq. 7) and R_eq
-    from the liquid area.  Runs on the GPU through the library."""
+    from the liquid area.  `width` is the initial tanh interface width (a
+    wider start is gentler at small tau).  Runs on the GPU through the
+    library."""
     inv_r, dps = [], []
 
     def pressure(r):
@@ -132,10 +135,13 @@ def laplace_sigma(lbm, G: float, tau: float, rho_l: float, rho_v: float,
 
     for R in radii:
         lat = lbm.Lattice(N, N, 1, tau, G, storage=storage)
-        lat.init_ligament(R0=float(R), amp_rel=0.0, wavelength=1.0, rho_l=rho_l, rho_v=rho_v)
+        lat.init_ligament(R0=float(R), amp_rel=0.0, wavelength=1.0, rho_l=rho_l, rho_v=rho_v,
+                          width=width)
         lat.step(steps)
         rho = lat.fields()["rho"].cpu().numpy()[0]
         lat.close()
+        if not np.isfinite(rho).all() or rho.min() <= 0.0:
+            raise RuntimeError(f"Laplace cylinder R={R} diverged at G={G}, tau={tau}")
         rin, rout = rho[N // 2, N // 2], rho[0, 0]
         area = ((rho - rout) / (rin - rout)).sum()
         inv_r.append(1.0 / math.sqrt(area / math.pi))

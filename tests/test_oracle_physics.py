@@ -37,6 +37,18 @@ def tau_from_oh(R0, rho_l, sigma, oh=0.1):
     return 0.5 + 3.0 * oh * math.sqrt(sigma * R0 / rho_l)
 
 
+def test_workloads_table1_matches_golden():
+    """The sweep's parameters in workloads.py are the golden Table 1, with tau
+    from Oh = 0.1 as read here."""
+    assert [tuple(r) for r in workloads.TABLE1] == table1()
+    for R0, rl, _, sg in table1():
+        assert workloads.table1_tau(R0) == pytest.approx(tau_from_oh(R0, rl, sg), rel=1e-15)
+        s = workloads.paper_table1(R0)
+        assert (s.G, s.amp_rel, s.R0) == (-5.3, 0.1, float(R0))
+        assert s.nx == s.ny == workloads.round_half_up(4 * R0)
+        assert 0.69 < 2 * math.pi * R0 / s.nz < 0.71  # kR = 0.7 up to rounding of L
+
+
 def sc94_construction(G):
     """Equal-area rule with weight psi'/psi^2 for P = rho/3 + G psi^2/6, psi = 1 - e^-rho."""
     psi = lambda r: 1.0 - math.exp(-r)

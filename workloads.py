@@ -17,7 +17,9 @@ cosine-perturbed radius on a periodic box; Section 4 parameters):
 * ``batch64``         64 ligaments drawn from numpy ``default_rng(seed)``:
                       R0 ~ U[6,20], kR ~ U[0.3,0.9], tau ~ U[0.6,1.2],
                       G ~ U[-6,-5]; grid (round 4R)^2 x round(2 pi R / kR).
-* ``paper_table1``    the paper's sweep, G = -5.3, Oh = 0.1 (Table 1).
+* ``paper_table1(R0)`` the paper's sweep (Section 4, Table 1): G = -5.3,
+                      tau from Oh = 0.1, R0 in {7, 14, ..., 84}, grid as for
+                      ``convergence``.
 
 ``rho_l``/``rho_v`` of None mean "the flat-interface coexistence densities at
 this (G, tau)", which each side computes itself.
@@ -102,7 +104,38 @@ def batch64(seed: int = 2024, count: int = 64) -> list[Ligament]:
 
 
 # The paper's Table 1 (Section 4): G0 = 5.3 (attractive, G = -5.3), Oh = 0.1.
-TABLE1_R0 = (7, 14, 28, 42, 56, 70, 84)
+# Rows (R0, rho_l, rho_v, sigma) as printed.
+TABLE1 = (
+    (7, 2.112, 0.081, 0.05159),
+    (14, 2.117, 0.084, 0.05345),
+    (28, 2.125, 0.090, 0.05775),
+    (42, 2.135, 0.097, 0.06277),
+    (56, 2.145, 0.106, 0.06848),
+    (70, 2.156, 0.116, 0.07491),
+    (84, 2.167, 0.126, 0.08206),
+)
+TABLE1_R0 = tuple(r[0] for r in TABLE1)
+TABLE1_G = -5.3
+TABLE1_OH = 0.1
+
+
+def table1_tau(R0: int) -> float:
+    """tau of a Table 1 row: Oh = nu sqrt(rho_l / (sigma R0)) = 0.1 with the
+    row's printed rho_l and sigma, nu = (tau - 1/2) / 3 (Eq. (8) with the
+    square root that makes it dimensionless)."""
+    _, rho_l, _, sigma = {r[0]: r for r in TABLE1}[R0]
+    return 0.5 + 3.0 * TABLE1_OH * math.sqrt(sigma * R0 / rho_l)
+
+
+def paper_table1(R0: int) -> Ligament:
+    """A ligament of the paper's sweep: G = -5.3, tau from Oh = 0.1, radius R0
+    perturbed by R0/10 with one cosine wave along a z period of
+    round(2 pi R0 / 0.7) (kR = 0.7, inside the unstable band), cross-section
+    round(4 R0) squared, interface width 2, no noise."""
+    N = round_half_up(4 * R0)
+    L = round_half_up(2 * math.pi * R0 / 0.7)
+    return Ligament(f"paper R0={R0} {N}x{N}x{L}", N, N, L, tau=table1_tau(R0), G=TABLE1_G,
+                    R0=float(R0), wavelength=float(L), amp_rel=0.1)
 
 
 def random_populations(shape, seed: int, base: float = 1.0, spread: float = 0.1,
