@@ -294,7 +294,9 @@ int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
 /*
  * Autotuner of the batched launch: time each tile shape and z chunk (>= 4)
  * over the whole item list (launches from the current lattices into the
- * spare ones, so the state is unchanged) and keep the fastest.  Synchronous.
+ * spare ones, so the state is unchanged) and keep the fastest.
+ * *best_mlups counts the nodes of the cases that are not frozen.
+ * Synchronous.
  */
 int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *best,
                        double *best_mlups);

@@ -1284,8 +1284,14 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     double best_t = INFINITY;
     const lbm_launch orig = b->launch;
     lbm_launch bl = orig;
+    // throughput is counted over the cases that are not frozen (frozen ones exit at once)
+    std::vector<int32_t> fz(b->n, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(fz.data(), b->d_frozen, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     double nodes = 0;
-    for (int i = 0; i < b->n; ++i) nodes += double(b->p[i].nx) * b->p[i].ny * b->p[i].nz;
+    for (int i = 0; i < b->n; ++i)
+        if (fz[i] == 0) nodes += double(b->p[i].nx) * b->p[i].ny * b->p[i].nz;
     for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
         lbm_launch l;
         tile_shape(ti, &l.tile_x, &l.tile_y);
