@@ -278,12 +278,11 @@ def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, ex
     if extra_after:
         lat.step(extra_after)
     d = lat.diagnostics()
-    rho = lat.fields()["rho"].cpu().numpy()
-    drops = analysis.droplets(rho, 0.5 * (rho_l + rho_v))
+    drops = lat.droplets(0.5 * (rho_l + rho_v), max_out=8)  # labelled on the device
     lat.close()
-    return {"t_b": tb, "steps": lat.step_count if False else n_done + extra_after,
+    return {"t_b": tb, "steps": n_done + extra_after,
             "ms_per_step_incl_diag": round(ms_step, 4),
-            "droplets": drops.count, "volumes": drops.volumes[:8].tolist(),
+            "droplets": drops["count"], "volumes": drops["volumes"].tolist(),
             "mass_drift": (d["mass"] - m0) / m0, "nonfinite": d["nonfinite"]}
 
 

@@ -210,6 +210,30 @@ enum { LBM_DIAG_RING = 4096 };
 int lbm_record_diag(lbm_ctx *ctx);
 int lbm_read_diag_history(lbm_ctx *ctx, lbm_diag *out, int32_t max, int32_t *count);
 
+/*
+ * Droplets of the current state (the break-up analysis of Sections 3-4: the
+ * ligament pinches into a main drop and satellites): the 6-connected
+ * components of {rho > rho_mid} on the periodic grid, labelled on the device
+ * with a union-find.  Each component reports its volume (nodes), its mass
+ * (sum of rho, FP64; the last bits depend on the order of the device's
+ * atomic additions) and its first node, the smallest linear index
+ * (z * ny + y) * nx + x it contains.
+ *
+ * *count receives the number of components; the min(max_out, *count)
+ * largest (volume descending, then first node ascending) are copied to out
+ * (may be NULL when max_out is 0).  The per-node work arrays live in the
+ * spare lattice, which the next lbm_step overwrites anyway: the state is not
+ * touched and no device memory is allocated for them; a temporary device
+ * table of 24 bytes per component is allocated and freed.  Synchronises.
+ */
+typedef struct {
+    int64_t volume;
+    double mass;
+    int64_t first_node;
+} lbm_droplet;
+
+int lbm_droplets(lbm_ctx *ctx, double rho_mid, lbm_droplet *out, int32_t max_out, int64_t *count);
+
 /* Steps taken since the last lbm_init_ligament. */
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 

@@ -410,6 +410,159 @@ __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state
 }
 
 // Blocks for a row loop over a grid: one block per (y, z) row, capped.
+// ---------------------------------------------------------------------------
+// Droplets: 6-connected components of {rho > rho_mid} on the periodic grid
+// (the droplet count of the break-up analysis), labelled on the device by a
+// lock-free union-find over node indices.
+//
+// parent[i] is -1 for a background node and a node index <= i for a
+// foreground one; a root has parent[i] == i.  Every value ever stored keeps
+// parent[i] <= i (stores only lower it, to the smaller of two roots or to an
+// ancestor), so a find walks strictly decreasing indices and ends.  A union links the larger
+// root under the smaller with an atomic minimum; if the larger one had been
+// linked meanwhile, it retries with the value found there, which is smaller:
+// max(a, b) falls at every retry, so it ends as well.  When the union pass
+// has finished, each component is one tree whose root is its smallest node
+// index.  Loads of parent go to the device-coherent level (agent scope), so
+// a find never follows a value older than what this CU's cache held.
+
+__device__ inline int cc_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int cc_find(const int32_t *parent, int i) {
+    int p = cc_load(&parent[i]);
+    while (p != i) {
+        i = p;
+        p = cc_load(&parent[i]);
+    }
+    return i;
+}
+
+// Find with path halving: each visited node is re-pointed (atomic minimum, so
+// a lower value stored meanwhile is kept) at its grandparent, an ancestor in
+// the same tree.  Without it, row roots linked one after another form chains
+// as long as the number of rows in a large drop.
+__device__ inline int cc_find_halving(int32_t *parent, int x) {
+    while (true) {
+        const int p = cc_load(&parent[x]);
+        if (p == x) return x;
+        const int gp = cc_load(&parent[p]);
+        if (gp == p) return p;
+        atomicMin(&parent[x], gp);
+        x = gp;
+    }
+}
+
+__device__ inline void cc_union(int32_t *parent, int a, int b) {
+    while (true) {
+        a = cc_find_halving(parent, a);
+        b = cc_find_halving(parent, b);
+        if (a == b) return;
+        if (a > b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&parent[b], a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// Density of every node (FP64), the initial forest, zeroed per-root sums and
+// the two counters of the compaction.
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_cc_init(LatticeRef L, double rho_mid, double *__restrict__ rho,
+                                                    int32_t *__restrict__ parent, int32_t *__restrict__ vol,
+                                                    double *__restrict__ mass, int32_t *__restrict__ counters) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
+    LBM_FOR_EACH_NODE(L) {
+        double f[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[a] = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+        const double r = density(f);
+        rho[i] = r;
+        parent[i] = r > rho_mid ? int32_t(i) : -1;  // NaN is background
+        vol[i] = 0;
+        mass[i] = 0.0;
+    }
+}
+
+// Union of every foreground node with its +x, +y and +z neighbours (periodic);
+// the -x, -y, -z links are the same pairs seen from the other node.
+__global__ __launch_bounds__(kBlock) void k_cc_union(int32_t *parent, int nx, int ny, int nz) {
+    for (int row = blockIdx.x; row < ny * nz; row += gridDim.x) {
+        const int y = row % ny, z = row / ny;
+        const int yn = y + 1 == ny ? 0 : y + 1, zn = z + 1 == nz ? 0 : z + 1;
+        for (int x = threadIdx.x; x < nx; x += kBlock) {
+            const int i = row * nx + x;
+            if (cc_load(&parent[i]) < 0) continue;
+            const int xn = x + 1 == nx ? 0 : x + 1;
+            const int nb[3] = {row * nx + xn, (z * ny + yn) * nx + x, (zn * ny + y) * nx + x};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (cc_load(&parent[nb[k]]) >= 0) cc_union(parent, i, nb[k]);
+        }
+    }
+}
+
+// Every foreground node points at its root.
+__global__ __launch_bounds__(kBlock) void k_cc_compress(int32_t *parent, int n) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        if (cc_load(&parent[i]) >= 0)
+            __hip_atomic_store(&parent[i], cc_find(parent, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Volume (nodes) and mass (sum of rho) per root.  The FP64 atomic sums make
+// the last bits of a mass depend on the order of the additions.
+__global__ __launch_bounds__(kBlock) void k_cc_accumulate(const int32_t *__restrict__ parent,
+                                                          const double *__restrict__ rho, int n,
+                                                          int32_t *vol, double *mass) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int r = parent[i];
+        if (r >= 0) {
+            atomicAdd(&vol[r], 1);
+            atomicAdd(&mass[r], rho[i]);
+        }
+    }
+}
+
+// Number of roots (nodes with a non-zero volume): one atomic per wave.
+__global__ __launch_bounds__(kBlock) void k_cc_count(const int32_t *__restrict__ vol, int n,
+                                                     int32_t *counter) {
+    const int lane = threadIdx.x & 63;
+    for (int base = (blockIdx.x * kBlock + threadIdx.x) & ~63; base < n; base += gridDim.x * kBlock) {
+        const int i = base + lane;
+        const unsigned long long m = __ballot(i < n && vol[i] > 0);
+        if (lane == 0 && m) atomicAdd(counter, int32_t(__popcll(m)));
+    }
+}
+
+// One table entry per root, in no particular order (the host sorts).
+__global__ __launch_bounds__(kBlock) void k_cc_write(const int32_t *__restrict__ vol,
+                                                     const double *__restrict__ mass, int n,
+                                                     int32_t *counter, DropletEntry *out, int cap) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int v = vol[i];
+        if (v > 0) {
+            const int k = atomicAdd(counter, 1);
+            if (k < cap) {
+                out[k].first_node = i;
+                out[k].volume = v;
+                out[k].mass = mass[i];
+            }
+        }
+    }
+}
+
+int flat_grid(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return int(b);
+}
+
 int rows_grid(const LatticeRef &L) {
     int64_t b = int64_t(L.ny) * L.nz;
     if (b > 65536) b = 65536;
@@ -494,6 +647,30 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) 
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffffull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy16, dim3(unsigned(nb)), dim3(kCopyBlock), 0, s, (u32x4 *)dst, (const u32x4 *)src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_droplets_label(const LatticeRef &L, double rho_mid, const DropletScratch &w, hipStream_t s) {
+    const int n = L.nx * L.ny * L.nz;
+    const int nb = rows_grid(L);
+    LBM_DISPATCH(L.storage, k_cc_init, dim3(nb), dim3(kBlock), 0, s, L, rho_mid, w.rho, w.parent, w.vol, w.mass,
+                 w.counters);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cc_union, dim3(nb), dim3(kBlock), 0, s, w.parent, L.nx, L.ny, L.nz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int fb = flat_grid(n);
+    hipLaunchKernelGGL(k_cc_compress, dim3(fb), dim3(kBlock), 0, s, w.parent, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cc_accumulate, dim3(fb), dim3(kBlock), 0, s, w.parent, w.rho, n, w.vol, w.mass);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cc_count, dim3(fb), dim3(kBlock), 0, s, w.vol, n, w.counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *out, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_write, dim3(flat_grid(n)), dim3(kBlock), 0, s, w.vol, w.mass, n, w.counters + 1, out,
+                       cap);
     return hipGetLastError();
 }
 

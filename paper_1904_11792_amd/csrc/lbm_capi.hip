@@ -10,6 +10,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
 #include <string>
 #include <vector>
 
@@ -693,6 +696,61 @@ int lbm_diagnostics(lbm_ctx *c, lbm_diag *out) {
     if (r.nonfinite > 0)
         return fail(LBM_ERR_DIVERGED, "%lld nodes non-finite or with rho <= 0 at step %lld",
                     (long long)r.nonfinite, (long long)r.step);
+    return LBM_OK;
+}
+
+static_assert(sizeof(lbm_droplet) == sizeof(DropletEntry) &&
+                  offsetof(lbm_droplet, volume) == offsetof(DropletEntry, volume) &&
+                  offsetof(lbm_droplet, mass) == offsetof(DropletEntry, mass) &&
+                  offsetof(lbm_droplet, first_node) == offsetof(DropletEntry, first_node),
+              "lbm_droplet mirrors the device table entry");
+
+int lbm_droplets(lbm_ctx *c, double rho_mid, lbm_droplet *out, int32_t max_out, int64_t *count) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (!count) return fail(LBM_ERR_INVALID_ARG, "count is NULL");
+    if (max_out < 0) return fail(LBM_ERR_INVALID_ARG, "max_out must be >= 0");
+    if (max_out > 0 && !out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    if (!std::isfinite(rho_mid)) return fail(LBM_ERR_INVALID_ARG, "rho_mid must be finite");
+    if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
+    const int64_t n = int64_t(c->p.nx) * c->p.ny * c->p.nz;
+    // Work arrays in the spare lattice (19 n b >= 38 n bytes): rho and mass
+    // (8 n each), parent and volume (4 n each), two counters.
+    char *w0 = static_cast<char *>(c->lat[c->cur ^ 1]);
+    if (size_t(24 * n + 8) > c->lay.lat_bytes) return fail(LBM_ERR_INVALID_ARG, "spare lattice too small");
+    DropletScratch w;
+    w.rho = reinterpret_cast<double *>(w0);
+    w.mass = reinterpret_cast<double *>(w0 + 8 * n);
+    w.parent = reinterpret_cast<int32_t *>(w0 + 16 * n);
+    w.vol = reinterpret_cast<int32_t *>(w0 + 20 * n);
+    w.counters = reinterpret_cast<int32_t *>(w0 + 24 * n);
+    int32_t ncomp = 0;
+    hipError_t e = launch_droplets_label(lattice_ref(c, c->cur), rho_mid, w, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ncomp, w.counters, sizeof(ncomp), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<DropletEntry> table(size_t(ncomp > 0 ? ncomp : 0));
+    if (e == hipSuccess && ncomp > 0) {
+        DropletEntry *d = nullptr;
+        e = hipMalloc(&d, sizeof(DropletEntry) * size_t(ncomp));
+        if (e == hipSuccess) e = launch_droplets_table(w, int(n), d, ncomp, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(table.data(), d, sizeof(DropletEntry) * size_t(ncomp), hipMemcpyDeviceToHost,
+                               c->stream);
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = e2;
+        if (d) (void)hipFree(d);
+    }
+    if (e != hipSuccess) return device_fail(c, e, "lbm_droplets");
+    std::sort(table.begin(), table.end(), [](const DropletEntry &a, const DropletEntry &b) {
+        return a.volume != b.volume ? a.volume > b.volume : a.first_node < b.first_node;
+    });
+    *count = ncomp;
+    const int64_t k = ncomp < max_out ? ncomp : max_out;
+    for (int64_t i = 0; i < k; ++i) {
+        out[i].volume = table[i].volume;
+        out[i].mass = table[i].mass;
+        out[i].first_node = table[i].first_node;
+    }
     return LBM_OK;
 }
 

@@ -58,6 +58,21 @@ struct LatticeRef {
     void *pair[2];
 };
 
+// One component of the droplet labelling (mirrors lbm_droplet).
+struct DropletEntry {
+    int64_t volume;
+    double mass;
+    int64_t first_node;
+};
+
+// Device arrays of the droplet labelling over n nodes (carved from the
+// spare lattice by the host): FP64 density and per-root mass, int32 parent
+// and per-root volume, and two int32 counters.
+struct DropletScratch {
+    double *rho, *mass;
+    int32_t *parent, *vol, *counters;
+};
+
 struct LigamentArgs {
     int axis;
     double R0, amp_rel, wavelength, c1, c2, width, rho_l, rho_v, noise_amp;
@@ -93,6 +108,11 @@ hipError_t launch_diag(const LatticeRef &L, int axis, DiagPartial *partials,
                        int32_t *frozen_flag, int32_t freeze_value, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long v,
                            hipStream_t s);
+// Droplet labelling of the lattice L (6-connected components of rho > rho_mid,
+// periodic); leaves the number of components in w.counters[0].
+hipError_t launch_droplets_label(const LatticeRef &L, double rho_mid, const DropletScratch &w, hipStream_t s);
+// Writes one entry per component (at most cap) into out, in no particular order.
+hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *out, int cap, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Flat-interface coexistence run: `chunk` steps on the 1 x 1 x n slab held in
 // `state` ([19][n] doubles); init != 0 first writes the start profile

@@ -14,6 +14,7 @@ import ctypes
 import math
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +69,10 @@ class lbm_diag(ctypes.Structure):
                 "nonfinite": int(self.nonfinite)}
 
 
+class lbm_droplet(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_int64), ("mass", ctypes.c_double), ("first_node", ctypes.c_int64)]
+
+
 class lbm_launch(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("zchunk", ctypes.c_int32)]
 
@@ -90,6 +95,7 @@ _SIGS = {
     "lbm_record_diag": (ctypes.c_int, [_vp]),
     "lbm_read_diag_history": (ctypes.c_int, [_vp, _P(lbm_diag), _i32, _P(_i32)]),
     "lbm_get_step": (ctypes.c_int, [_vp, _P(_i64)]),
+    "lbm_droplets": (ctypes.c_int, [_vp, _d, _P(lbm_droplet), _i32, _P(_i64)]),
     "lbm_set_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_get_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_list_tiles": (ctypes.c_int, [_P(lbm_launch), _i32, _P(_i32)]),
@@ -184,6 +190,13 @@ def lbm_diagnostics(ctx) -> tuple[int, lbm_diag]:
     d = lbm_diag()
     st = _check(_lib.lbm_diagnostics(ctx, ctypes.byref(d)), ok=(LBM_OK, LBM_ERR_DIVERGED))
     return st, d
+
+
+def lbm_droplets(ctx, rho_mid: float, max_out: int = 1024) -> tuple[int, list[lbm_droplet]]:
+    buf = (lbm_droplet * max(max_out, 1))()
+    cnt = _i64()
+    _check(_lib.lbm_droplets(ctx, float(rho_mid), buf, int(max_out), ctypes.byref(cnt)))
+    return int(cnt.value), [buf[i] for i in range(min(int(cnt.value), max_out))]
 
 
 def lbm_set_axis(ctx, axis: int) -> None:
@@ -345,6 +358,15 @@ class Lattice:
 
     def set_axis(self, axis: int) -> None:
         lbm_set_axis(self.ctx, axis)
+
+    def droplets(self, rho_mid: float, max_out: int = 1024) -> dict:
+        """Components of rho > rho_mid labelled on the device: count, and for
+        the max_out largest their volumes, masses and first nodes."""
+        count, items = lbm_droplets(self.ctx, rho_mid, max_out)
+        return {"count": count,
+                "volumes": np.array([d.volume for d in items], dtype=np.int64),
+                "masses": np.array([d.mass for d in items], dtype=np.float64),
+                "first_nodes": np.array([d.first_node for d in items], dtype=np.int64)}
 
     def record_diag(self) -> None:
         lbm_record_diag(self.ctx)

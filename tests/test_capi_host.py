@@ -93,6 +93,9 @@ def test_null_handles_are_rejected(lbm):
         lbm.lbm_destroy(None)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_diagnostics(None)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_droplets(None, 1.0)
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG
 
 
 def test_batch_validation(lbm):
