@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--form", default="single",
                     choices=["single", "batch", "precision", "convergence", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
+                    help="mrt: the multiple-relaxation-time collision with the suggested rates "
+                         "of d'Humieres et al. and s_j = 1/tau")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
     ap.add_argument("--sweep", action="store_true",
@@ -167,8 +170,11 @@ def main():
     spec = workloads.LARGE_FP32
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
     rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+    mrt = {} if args.collision == "mrt" else None
+    if mrt is not None:
+        rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau, mrt=mrt)
     lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=args.storage,
-                      rho_ref=rho_v, stream=stream)
+                      rho_ref=rho_v, stream=stream, mrt=mrt)
     lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength,
                       rho_l=rho_l, rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
     if args.sweep:
@@ -207,13 +213,14 @@ def main():
     d = lat.diagnostics()
     alg_bytes = 2 * 19 * BYTES_PER_POP[args.storage] * spec.n
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.storage, spec.n)
+    traffic = measured_traffic(args.storage, spec.n) if mrt is None else None
     out = {
         "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
-        "config": {"workload": spec.name + f" R0=24 tau=0.8 G=-5.5 storage={args.storage}",
+        "config": {"workload": spec.name + f" R0=24 tau=0.8 G=-5.5 storage={args.storage}"
+                               + (" collision=mrt" if mrt is not None else ""),
                    "grid": [spec.nx, spec.ny, spec.nz], "launch": list(launch),
                    "graph_chunk": args.graph_chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -224,7 +231,7 @@ def main():
     }
     print(f"# {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s",
           file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and mrt is None:
         out["cpu_baseline"] = cpu_baseline(spec, rho_l, rho_v)
     print(json.dumps(out), flush=True)
 
@@ -256,7 +263,8 @@ def sweep(lat, spec, stream, storage):
               f" | {bpn * spec.n / best / 1e6:.0f} |", flush=True)
 
 
-def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, extra_after=0):
+def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, extra_after=0,
+                  mrt=None):
     """Step one ligament to break-up (neck sampled every `every` steps), then
     `extra_after` more steps; returns t_b, time per step, droplets, mass drift."""
     import torch
@@ -264,7 +272,7 @@ def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, ex
     from paper_1904_11792_amd import analysis
 
     lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage, rho_ref=rho_v,
-                      stream=stream)
+                      stream=stream, mrt=mrt)
     lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength, rho_l=rho_l,
                       rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
     m0 = lat.diagnostics()["mass"]
@@ -360,10 +368,18 @@ def study_paper(args, lbm, workloads, stream):
     Per radius: flat-interface coexistence and Laplace surface tension on the
     GPU against Table 1, then the ligament (FP32 storage unless --storage
     says otherwise) run to break-up: t_b / t_cap against R0, the trend the
-    paper's Fig. 2 shows (its data points are not printed)."""
+    paper's Fig. 2 shows (its data points are not printed).
+
+    With --collision mrt: the comparison the paper's conclusion proposes, the
+    same sweep with the MRT collision at s_j and the other non-viscous rates
+    fixed to 1, which keeps the density ratio (and sigma) the same at every
+    viscosity: one coexistence and one Laplace fit serve all radii, and tau
+    follows from Oh = 0.1 with them."""
     from paper_1904_11792_amd import analysis
 
     storage = args.storage
+    if args.collision == "mrt":
+        return study_paper_mrt(args, lbm, workloads, stream, analysis)
     rows = []
     for R0, rl_p, rv_p, sg_p in workloads.TABLE1:
         spec = workloads.paper_table1(R0)
@@ -392,6 +408,33 @@ def study_paper(args, lbm, workloads, stream):
         rows.append(r)
         print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
     print(json.dumps({"study": "paper_table1", "G": workloads.TABLE1_G, "Oh": workloads.TABLE1_OH,
+                      "rows": rows}))
+
+
+def study_paper_mrt(args, lbm, workloads, stream, analysis):
+    import dataclasses
+
+    mrt = {k: 1.0 for k in ("s_e", "s_eps", "s_q", "s_pi", "s_m", "s_j")}
+    G = workloads.TABLE1_G
+    rho_l, rho_v = lbm.lbm_coexistence(G, 1.0, mrt=mrt)
+    sigma, icpt = analysis.laplace_sigma(lbm, G, 1.0, rho_l, rho_v, width=4.0, mrt=mrt)
+    print(f"# MRT G={G}: rho_l={rho_l:.6f} rho_v={rho_v:.6f} sigma={sigma:.5f}", file=sys.stderr, flush=True)
+    rows = []
+    for R0, _, _, _ in workloads.TABLE1:
+        tau = analysis.tau_for_ohnesorge(workloads.TABLE1_OH, rho_l, sigma, R0)
+        spec = dataclasses.replace(workloads.paper_table1(R0), tau=tau)
+        co_l, co_v = lbm.lbm_coexistence(G, tau, mrt=mrt)  # the same densities at this tau
+        tcap = analysis.capillary_time(rho_l, R0, sigma)
+        print(f"# R0={R0} tau={tau:.4f} grid {spec.nx}x{spec.ny}x{spec.nz}", file=sys.stderr, flush=True)
+        r = _run_ligament(lbm, spec, args.storage, rho_l, rho_v, stream, max_steps=int(40 * tcap) + 2000,
+                          every=max(1, R0 // 8), mrt=mrt)
+        r.update({"R0": R0, "grid": [spec.nx, spec.ny, spec.nz], "tau": tau, "storage": args.storage,
+                  "rho_l_at_tau": co_l, "rho_v_at_tau": co_v, "t_cap": tcap,
+                  "t_b_over_t_cap": None if r["t_b"] is None else r["t_b"] / tcap})
+        rows.append(r)
+        print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "paper_table1_mrt", "G": G, "Oh": workloads.TABLE1_OH, "mrt": mrt,
+                      "rho_l": rho_l, "rho_v": rho_v, "sigma": sigma, "laplace_intercept": icpt,
                       "rows": rows}))
 
 

@@ -118,6 +118,44 @@ int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_
                     double *rho_v);
 
 /*
+ * Multiple-relaxation-time (MRT) collision, the operator the paper's
+ * conclusion names as future work (it lets the viscosity change at a fixed
+ * density ratio; the paper gives no details).  Moment basis of d'Humieres,
+ * Ginzburg, Krafczyk, Lallemand and Luo (Phil. Trans. R. Soc. A 360, 2002)
+ * for D3Q19: rho, e, eps, j, q, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz,
+ * m.  Equilibrium moments: those of the second-order equilibrium of Eq. (2),
+ * so that all rates equal to 1/tau give BGK.  The viscous moments (p_xx,
+ * p_ww, p_xy, p_yz, p_xz) relax at 1/tau: nu = (tau - 1/2)/3 as for BGK;
+ * the bulk viscosity is (2/9)(1/s_e - 1/2).  The force enters as the
+ * velocity shift of Eq. (6) in moment space: the equilibrium is taken at
+ * momentum j + F / s_j.  Every rate lies in (0, 2); s_j <= 0 selects
+ * s_j = 1/tau (the BGK shift u + tau F / rho).  d'Humieres et al. suggest
+ * s_e = 1.19, s_eps = s_pi = 1.4, s_q = 1.2, s_m = 1.98.
+ */
+typedef struct {
+    double s_e, s_eps, s_q, s_pi, s_m, s_j;
+} lbm_mrt;
+
+/*
+ * lbm_coexistence with the MRT collision at these rates (the tau stages
+ * change only the viscous rate).  Errors as lbm_coexistence; INVALID_ARG for
+ * rates outside (0, 2).
+ */
+int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, double rho0,
+                        double *rho_l, double *rho_v);
+
+/*
+ * Select the collision of a context: mrt = NULL for BGK (the default), else
+ * the MRT rates above (copied).  The MRT kernels are compiled for the
+ * run-time tiles (tile_x = 0); if the current launch uses a compile-time
+ * tile it is reset to the default launch, and lbm_set_launch then refuses
+ * compile-time tiles with UNSUPPORTED.  lbm_init_ligament with rho_l or
+ * rho_v <= 0 takes the coexistence densities of the selected collision.
+ * Captured graphs are rebuilt.  The batched form uses BGK.
+ */
+int lbm_set_mrt(lbm_ctx *ctx, const lbm_mrt *mrt);
+
+/*
  * Equal-area (mechanical stability) construction for the equation of state
  * of Eq. (7), P = rho c_s^2 + c_s^2 G psi^2 / 2: the densities with
  * P(rho_v) = P(rho_l) = p whose integral of (p - P) psi'/psi^2 between them

@@ -8,7 +8,10 @@ The arithmetic lives in ``sc_oracle.c`` (plain C, FP64, OpenMP over z); this
 module is a ctypes wrapper plus the slow drivers built on it:
 
 * ``step`` / ``run``          -- Eq. (3) with the velocity shift of Eq. (6)
-                                 (Section 2 of the paper)
+                                 (Section 2 of the paper); with ``mrt=`` the
+                                 multiple-relaxation-time collision the
+                                 paper's conclusion names (see sc_oracle.c)
+* ``mrt_matrix`` / ``mrt_equilibrium`` / ``mrt_rates`` -- its ingredients
 * ``fields``                  -- rho, j (Eq. 4), F (Eq. 5), physical velocity
 * ``init_ligament``           -- the perturbed cylinder of Section 3 (Fig. 1)
 * ``diag``                    -- mass, momentum, rho range, neck density
@@ -71,6 +74,12 @@ def lib():
     L.orc_step.restype = ci
     L.orc_run.argtypes = [ci, ci, ci, cd, cd, cd, cl, dp, dp]
     L.orc_run.restype = ci
+    L.orc_mrt_matrix.argtypes = [dp]
+    L.orc_mrt_matrix.restype = None
+    L.orc_mrt_equilibrium.argtypes = [cd, cd, cd, cd, dp]
+    L.orc_mrt_equilibrium.restype = None
+    L.orc_run_mrt.argtypes = [ci, ci, ci, dp, cd, cd, cl, dp, dp]
+    L.orc_run_mrt.restype = ci
     L.orc_fields.argtypes = [ci, ci, ci, cd, cd, dp, dp, dp, dp, dp]
     L.orc_fields.restype = ci
     L.orc_splitmix64.argtypes = [cu64]
@@ -131,8 +140,40 @@ def feq(rho: float, u) -> np.ndarray:
     return out
 
 
-def step(f: np.ndarray, tau: float, G: float, rho0: float = 1.0) -> np.ndarray:
+# Rates of d'Humieres et al. (2002) for the non-hydrodynamic moments.
+MRT_DEFAULT = {"s_e": 1.19, "s_eps": 1.4, "s_q": 1.2, "s_pi": 1.4, "s_m": 1.98}
+
+
+def mrt_matrix() -> np.ndarray:
+    """The 19 x 19 moment matrix M (rows: rho, e, eps, jx, qx, jy, qy, jz, qz,
+    3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz)."""
+    M = np.empty((Q, Q))
+    lib().orc_mrt_matrix(_dp(M))
+    return M
+
+
+def mrt_equilibrium(rho: float, j) -> np.ndarray:
+    out = np.empty(Q)
+    lib().orc_mrt_equilibrium(float(rho), float(j[0]), float(j[1]), float(j[2]), _dp(out))
+    return out
+
+
+def mrt_rates(tau: float, mrt: dict) -> np.ndarray:
+    """Rate of every moment: the viscous moments (3pxx, pww, pxy, pyz, pxz)
+    relax at 1/tau; the others as given in ``mrt`` (keys s_e, s_eps, s_q,
+    s_pi, s_m, s_j; defaults MRT_DEFAULT and s_j = 1/tau)."""
+    r = dict(MRT_DEFAULT)
+    r["s_j"] = 1.0 / tau
+    r.update(mrt)
+    nu = 1.0 / tau
+    return np.array([0.0, r["s_e"], r["s_eps"], r["s_j"], r["s_q"], r["s_j"], r["s_q"], r["s_j"],
+                     r["s_q"], nu, r["s_pi"], nu, r["s_pi"], nu, nu, nu, r["s_m"], r["s_m"], r["s_m"]])
+
+
+def step(f: np.ndarray, tau: float, G: float, rho0: float = 1.0, mrt: dict | None = None) -> np.ndarray:
     """One update; returns a new array."""
+    if mrt is not None:
+        return run(f, 1, tau, G, rho0, mrt)
     f = np.ascontiguousarray(f, dtype=np.float64)
     nx, ny, nz = _shape(f)
     out = np.empty_like(f)
@@ -141,12 +182,19 @@ def step(f: np.ndarray, tau: float, G: float, rho0: float = 1.0) -> np.ndarray:
     return out
 
 
-def run(f: np.ndarray, nsteps: int, tau: float, G: float, rho0: float = 1.0) -> np.ndarray:
-    """nsteps updates; returns a new array (the input is left untouched)."""
+def run(f: np.ndarray, nsteps: int, tau: float, G: float, rho0: float = 1.0,
+        mrt: dict | None = None) -> np.ndarray:
+    """nsteps updates; returns a new array (the input is left untouched).
+    ``mrt``: None for BGK, else the rates of the MRT collision (``mrt_rates``)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     nx, ny, nz = _shape(f)
     scratch = np.empty_like(f)
-    if lib().orc_run(nx, ny, nz, tau, G, rho0, int(nsteps), _dp(f), _dp(scratch)) != 0:
+    if mrt is None:
+        rc = lib().orc_run(nx, ny, nz, tau, G, rho0, int(nsteps), _dp(f), _dp(scratch))
+    else:
+        s = mrt_rates(tau, mrt)
+        rc = lib().orc_run_mrt(nx, ny, nz, _dp(s), G, rho0, int(nsteps), _dp(f), _dp(scratch))
+    if rc != 0:
         raise MemoryError("oracle run failed")
     return f
 
@@ -256,7 +304,8 @@ def equal_area(G: float, rho0: float = 1.0):
 def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
                 tol: float = 1e-12, chunk: int = 1000, max_steps: int = 200_000,
                 rho_hi: float | None = None, rho_lo: float | None = None,
-                width: float = 4.0, tau_step: float = 0.05) -> Coexistence:
+                width: float = 4.0, tau_step: float = 0.05,
+                mrt: dict | None = None) -> Coexistence:
     """Coexisting densities from a flat interface on a 1 x 1 x n periodic slab.
 
     Start: densities hi/lo of the equal-area construction (``equal_area``)
@@ -280,6 +329,9 @@ def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
     ``max_steps``.  The state with the smallest residual is reported: liquid
     density at z = n/2, vapour at z = 0.  The velocity-shift forcing makes
     these depend on tau as well as on G.
+
+    ``mrt``: run the slab with the MRT collision at these rates (the stages
+    then change only the viscous rate 1/tau).
     """
     if rho_hi is None or rho_lo is None:
         rho_hi, rho_lo = equal_area(G, rho0)
@@ -301,7 +353,7 @@ def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
     prev = rho.copy()
     for t in stages:  # relaxation stages
         for _ in range(100):
-            f = run(f, chunk, t, G, rho0)
+            f = run(f, chunk, t, G, rho0, mrt)
             cur = f.sum(axis=0)[:, 0, 0]
             if not np.all(np.isfinite(cur)):
                 return diverged
@@ -312,7 +364,7 @@ def coexistence(G: float, tau: float, rho0: float = 1.0, n: int = 128,
     best = (np.inf, 0, float(prev[n // 2]), float(prev[0]))
     steps = 0
     while steps < max_steps:
-        f = run(f, chunk, tau, G, rho0)
+        f = run(f, chunk, tau, G, rho0, mrt)
         steps += chunk
         cur = f.sum(axis=0)[:, 0, 0]
         if not np.all(np.isfinite(cur)):

@@ -230,6 +230,156 @@ int orc_run(int nx, int ny, int nz, double tau, double G, double rho0, long nste
 }
 
 /*
+ * Multiple-relaxation-time collision: the variant the paper's conclusion
+ * names as future work (collision operators other than BGK, which would let
+ * the viscosity change at a fixed density ratio).  The paper gives no
+ * details; this follows the D3Q19 moment basis of d'Humieres, Ginzburg,
+ * Krafczyk, Lallemand and Luo (Phil. Trans. R. Soc. A 360, 2002), with the
+ * equilibrium moments that are the projections of the second-order
+ * equilibrium of Eq. (2), so that equal rates reproduce BGK.
+ *
+ * Moments, in order: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww,
+ * piww, pxy, pyz, pxz, mx, my, mz; row k of M is the polynomial of c that
+ * defines moment k (mrt_row below), m = M f.
+ *
+ * Force: the velocity shift of Eq. (6) carried over to moment space: the
+ * equilibrium moments are evaluated at the momentum j' = j + F / s_j, s_j the
+ * rate of the momentum moments, so one collision adds exactly F to j (as
+ * BGK with s_j = 1/tau does).
+ *
+ * s[19] holds the rate of every moment (s[0] is irrelevant: rho is its own
+ * equilibrium).
+ */
+static double mrt_row(int k, int a)
+{
+    double x = CXO[a], y = CYO[a], z = CZO[a];
+    double c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * c2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * c2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * c2 - 9.0) * z;
+    case 9: return 3.0 * x * x - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+    }
+}
+
+/* The matrix M, row-major [19][19]. */
+void orc_mrt_matrix(double *M)
+{
+    for (int k = 0; k < Q; ++k)
+        for (int a = 0; a < Q; ++a) M[k * Q + a] = mrt_row(k, a);
+}
+
+/* Equilibrium moments at density rho and momentum (jx, jy, jz). */
+void orc_mrt_equilibrium(double rho, double jx, double jy, double jz, double *meq)
+{
+    double jj = jx * jx + jy * jy + jz * jz;
+    meq[0] = rho;
+    meq[1] = -11.0 * rho + 19.0 * jj / rho;
+    meq[2] = 3.0 * rho - 5.5 * jj / rho;
+    meq[3] = jx;
+    meq[4] = -2.0 / 3.0 * jx;
+    meq[5] = jy;
+    meq[6] = -2.0 / 3.0 * jy;
+    meq[7] = jz;
+    meq[8] = -2.0 / 3.0 * jz;
+    meq[9] = (3.0 * jx * jx - jj) / rho;
+    meq[10] = -0.5 * meq[9];
+    meq[11] = (jy * jy - jz * jz) / rho;
+    meq[12] = -0.5 * meq[11];
+    meq[13] = jx * jy / rho;
+    meq[14] = jy * jz / rho;
+    meq[15] = jx * jz / rho;
+    meq[16] = meq[17] = meq[18] = 0.0;
+}
+
+/*
+ * One step with the MRT collision: rho, psi everywhere; per node F (Eq. 5),
+ * m = M f, m* = m - S (m - m^eq(rho, j + F/s_j)), f* = M^-1 m* (M has
+ * orthogonal rows, so M^-1 = M^T diag(1/|row|^2)), fnext_a(x + c_a) = f*_a.
+ */
+void orc_step_mrt_ws(int nx, int ny, int nz, const double *s, double G, double rho0,
+                     const double *f, double *fnext, double *rho_work, double *psi_work)
+{
+    size_t n = (size_t)nx * ny * nz;
+    double M[Q][Q], norm[Q];
+    for (int k = 0; k < Q; ++k) {
+        norm[k] = 0.0;
+        for (int a = 0; a < Q; ++a) {
+            M[k][a] = mrt_row(k, a);
+            norm[k] += M[k][a] * M[k][a];
+        }
+    }
+    density_field(nx, ny, nz, f, rho_work);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < (long)n; ++i) psi_work[i] = orc_psi(rho_work[i], rho0);
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z) {
+        for (int y = 0; y < ny; ++y) {
+            for (int x = 0; x < nx; ++x) {
+                size_t i = node(x, y, z, nx, ny);
+                double fl[Q], m[Q], meq[Q], F[3];
+                for (int a = 0; a < Q; ++a) fl[a] = f[(size_t)a * n + i];
+                for (int k = 0; k < Q; ++k) {
+                    m[k] = 0.0;
+                    for (int a = 0; a < Q; ++a) m[k] += M[k][a] * fl[a];
+                }
+                force_at(x, y, z, nx, ny, nz, G, psi_work, F);
+                orc_mrt_equilibrium(m[0], m[3] + F[0] / s[3], m[5] + F[1] / s[5], m[7] + F[2] / s[7], meq);
+                for (int k = 0; k < Q; ++k) m[k] -= s[k] * (m[k] - meq[k]);
+                for (int a = 0; a < Q; ++a) {
+                    double fs = 0.0;
+                    for (int k = 0; k < Q; ++k) fs += M[k][a] * m[k] / norm[k];
+                    size_t d = node(wrap(x + CXO[a], nx), wrap(y + CYO[a], ny),
+                                    wrap(z + CZO[a], nz), nx, ny);
+                    fnext[(size_t)a * n + d] = fs;
+                }
+            }
+        }
+    }
+}
+
+/* nsteps MRT updates in place on f (fnext is scratch of the same size). */
+int orc_run_mrt(int nx, int ny, int nz, const double *s, double G, double rho0, long nsteps,
+                double *f, double *scratch)
+{
+    size_t n = (size_t)nx * ny * nz;
+    double *rho = (double *)malloc(n * sizeof(double));
+    double *psi = (double *)malloc(n * sizeof(double));
+    if (!rho || !psi) {
+        free(rho);
+        free(psi);
+        return -1;
+    }
+    double *a = f, *b = scratch;
+    for (long t = 0; t < nsteps; ++t) {
+        orc_step_mrt_ws(nx, ny, nz, s, G, rho0, a, b, rho, psi);
+        double *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    if (a != f) memcpy(f, a, (size_t)Q * n * sizeof(double));
+    free(rho);
+    free(psi);
+    return 0;
+}
+
+/*
  * Macroscopic fields of a state: rho (Eq. 4), bare momentum j = sum_a c_a f_a
  * (Eq. 4), force F (Eq. 5), and the physical velocity (j + F/2)/rho.
  * Any output pointer may be NULL.  Vector fields are [3][n].

@@ -120,13 +120,13 @@ def run_to_breakup(lat, rho_l: float, rho_v: float, max_steps: int, every: int =
 
 def laplace_sigma(lbm, G: float, tau: float, rho_l: float, rho_v: float,
                   radii=(10, 14, 18, 22), N: int = 80, steps: int = 8000, storage="f64",
-                  width: float = 2.0):
+                  width: float = 2.0, mrt: dict | None = None):
     """Surface tension from the Laplace law on quasi-2D cylinders (N x N x 1,
     periodic): fit dp = sigma / R_eq + b over several radii, with
     dp = P(rho_in) - P(rho_out) from the equation of state (Eq. 7) and R_eq
     from the liquid area.  `width` is the initial tanh interface width (a
-    wider start is gentler at small tau).  Runs on the GPU through the
-    library."""
+    wider start is gentler at small tau).  ``mrt``: MRT rates, or None for
+    BGK.  Runs on the GPU through the library."""
     inv_r, dps = [], []
 
     def pressure(r):
@@ -134,7 +134,7 @@ def laplace_sigma(lbm, G: float, tau: float, rho_l: float, rho_v: float,
         return r / 3.0 + G * psi * psi / 6.0
 
     for R in radii:
-        lat = lbm.Lattice(N, N, 1, tau, G, storage=storage)
+        lat = lbm.Lattice(N, N, 1, tau, G, storage=storage, mrt=mrt)
         lat.init_ligament(R0=float(R), amp_rel=0.0, wavelength=1.0, rho_l=rho_l, rho_v=rho_v,
                           width=width)
         lat.step(steps)

@@ -335,8 +335,9 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy16(u32x4 *__restrict__ dst, 
 // so the same force stencil and collision as the 3-D step apply unchanged.
 // State convention here: f_a(z, t) at z (push streaming inside LDS).
 __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state, int n, double G,
-                                                      double tau, double rho0, double hi, double lo,
-                                                      int chunk, int init, double *__restrict__ out) {
+                                                      double tau, double rho0, MrtParams mrt, double hi,
+                                                      double lo, int chunk, int init,
+                                                      double *__restrict__ out) {
     extern __shared__ double sm[];
     double *fa = sm;              // [19][n]
     double *fb = sm + Q * n;      // [19][n]
@@ -344,6 +345,7 @@ __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state
     double *red = psi + n;        // [n]
     const int z = threadIdx.x;
     const double inv_rho0 = 1.0 / rho0, omega = 1.0 / tau;
+    const MrtRates<double> rates = mrt_rates<double>(omega, mrt.s_e, mrt.s_eps, mrt.s_q, mrt.s_pi, mrt.s_m, mrt.s_j);
     if (z < n) {
         if (init) {
             const double W = 4.0;
@@ -374,7 +376,10 @@ __global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state
             auto P = [&](int, int, int dz) -> double { return psi[wrapi(z + dz, n)]; };
             double Fx, Fy, Fz;
             sc_force<double>(psi[z], G, P, Fx, Fy, Fz);
-            collide<double>(f, Fx, Fy, Fz, tau, omega);
+            if (mrt.on)
+                collide_mrt<double>(f, Fx, Fy, Fz, rates);
+            else
+                collide<double>(f, Fx, Fy, Fz, tau, omega);
 #pragma unroll
             for (int a = 0; a < Q; ++a) nxt[a * n + wrapi(z + kCZ[a], n)] = f[a];
         }
@@ -675,10 +680,10 @@ hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *o
 }
 
 hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    double hi, double lo, int chunk, int init, double *out,
-                                    hipStream_t s) {
+                                    const MrtParams &mrt, double hi, double lo, int chunk, int init,
+                                    double *out, hipStream_t s) {
     const size_t lds = sizeof(double) * (2 * Q * n + 2 * n);
-    hipLaunchKernelGGL(k_coexistence, dim3(1), dim3(n), lds, s, state, n, G, tau, rho0, hi, lo, chunk,
+    hipLaunchKernelGGL(k_coexistence, dim3(1), dim3(n), lds, s, state, n, G, tau, rho0, mrt, hi, lo, chunk,
                        init, out);
     return hipGetLastError();
 }

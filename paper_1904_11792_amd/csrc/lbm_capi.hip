@@ -233,6 +233,7 @@ struct lbm_ctx {
     int graph_chunk;
     hipGraphExec_t gexec;
     lbm_launch graph_launch;
+    MrtParams mrt;  // collision operator (mrt.on = 0: BGK)
 };
 
 namespace {
@@ -283,6 +284,7 @@ StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
     A.G = c->p.G;
     A.rho0 = c->p.rho0;
     A.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
+    A.mrt = c->mrt;
     return A;
 }
 
@@ -421,6 +423,7 @@ int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hi
     c->ring_written = c->ring_read = 0;
     c->graph_chunk = 0;
     c->gexec = nullptr;
+    c->mrt = MrtParams{};
     lbm_launch l;
     if (!cache_lookup(tune_key(p), &l) || check_launch(&l, p->nz) != LBM_OK) l = default_launch(p);
     c->launch = l;
@@ -512,8 +515,41 @@ int lbm_equal_area(double G, int32_t psi, double rho0, double *rho_l, double *rh
     return LBM_OK;
 }
 
-int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
+}  // extern "C"
+
+namespace {
+
+int check_mrt(const lbm_mrt *m) {
+    const double r[5] = {m->s_e, m->s_eps, m->s_q, m->s_pi, m->s_m};
+    for (double v : r)
+        if (!(v > 0.0 && v < 2.0)) return fail(LBM_ERR_INVALID_ARG, "MRT rates must lie in (0, 2)");
+    if (!(m->s_j < 2.0) || !std::isfinite(m->s_j))
+        return fail(LBM_ERR_INVALID_ARG, "s_j must be below 2 (or <= 0 for 1/tau)");
+    return LBM_OK;
+}
+
+MrtParams mrt_params(const lbm_mrt *m) {
+    MrtParams p{};
+    if (m) {
+        p.on = 1;
+        p.s_e = m->s_e;
+        p.s_eps = m->s_eps;
+        p.s_q = m->s_q;
+        p.s_pi = m->s_pi;
+        p.s_m = m->s_m;
+        p.s_j = m->s_j > 0.0 ? m->s_j : 0.0;
+    }
+    return p;
+}
+
+int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, double rho0, double *rho_l,
+                     double *rho_v) {
     if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
+    if (mrt_in) {
+        const int mst = check_mrt(mrt_in);
+        if (mst != LBM_OK) return mst;
+    }
+    const MrtParams mrt = mrt_params(mrt_in);
     if (psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", psi);
     if (!(tau > 0.5) || !isfinite(tau)) return fail(LBM_ERR_INVALID_ARG, "tau must be > 0.5");
     if (!(rho0 > 0.0) || !isfinite(rho0)) return fail(LBM_ERR_INVALID_ARG, "rho0 must be > 0");
@@ -538,7 +574,7 @@ int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_
     bool first = true;
     double out[4];
     auto run_chunk = [&](double t) -> hipError_t {
-        hipError_t err = launch_coexistence_chunk(d, n, G, t, rho0, start_l, start_v, chunk, first ? 1 : 0,
+        hipError_t err = launch_coexistence_chunk(d, n, G, t, rho0, mrt, start_l, start_v, chunk, first ? 1 : 0,
                                                   d + Q * n, nullptr);
         first = false;
         if (err == hipSuccess) err = hipMemcpy(out, d + Q * n, sizeof(out), hipMemcpyDeviceToHost);
@@ -583,6 +619,36 @@ int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_
     return LBM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
+    return coexistence_impl(G, tau, nullptr, psi, rho0, rho_l, rho_v);
+}
+
+int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, double rho0, double *rho_l,
+                        double *rho_v) {
+    if (!mrt) return fail(LBM_ERR_INVALID_ARG, "mrt is NULL");
+    return coexistence_impl(G, tau, mrt, psi, rho0, rho_l, rho_v);
+}
+
+int lbm_set_mrt(lbm_ctx *c, const lbm_mrt *mrt) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (mrt) {
+        st = check_mrt(mrt);
+        if (st != LBM_OK) return st;
+    }
+    c->mrt = mrt_params(mrt);
+    if (c->mrt.on && !tile_has_mrt(c->tile_index)) {
+        c->launch = default_launch(&c->p);  // a run-time tile, which has the MRT kernel
+        c->tile_index = find_tile(c->launch.tile_x, c->launch.tile_y);
+    }
+    release_graph(c);
+    return LBM_OK;
+}
+
 int lbm_init_ligament(lbm_ctx *c, const lbm_ligament *g) {
     int st = check_ctx(c);
     if (st != LBM_OK) return st;
@@ -605,7 +671,17 @@ int lbm_init_ligament(lbm_ctx *c, const lbm_ligament *g) {
     a.noise_amp = g->noise_amp;
     a.seed = g->seed;
     if (!(a.rho_l > 0) || !(a.rho_v > 0)) {
-        st = lbm_coexistence(c->p.G, c->p.tau, c->p.psi, c->p.rho0, &a.rho_l, &a.rho_v);
+        lbm_mrt m;
+        if (c->mrt.on) {
+            m.s_e = c->mrt.s_e;
+            m.s_eps = c->mrt.s_eps;
+            m.s_q = c->mrt.s_q;
+            m.s_pi = c->mrt.s_pi;
+            m.s_m = c->mrt.s_m;
+            m.s_j = c->mrt.s_j;
+        }
+        st = coexistence_impl(c->p.G, c->p.tau, c->mrt.on ? &m : nullptr, c->p.psi, c->p.rho0, &a.rho_l,
+                              &a.rho_v);
         if (st != LBM_OK) return st;
     }
     hipError_t e = launch_init_ligament(lattice_ref(c, 0), a, c->stream);
@@ -804,6 +880,8 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *l) {
     if (st != LBM_OK) return st;
     st = check_launch(l, c->p.nz);
     if (st != LBM_OK) return st;
+    if (c->mrt.on && !tile_has_mrt(find_tile(l->tile_x, l->tile_y)))
+        return fail(LBM_ERR_UNSUPPORTED, "the MRT collision runs on the run-time tiles (tile_x = 0) only");
     c->launch = *l;
     c->tile_index = find_tile(l->tile_x, l->tile_y);
     return LBM_OK;
@@ -842,6 +920,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, doub
         lbm_launch l;
         tile_shape(ti, &l.tile_x, &l.tile_y);
         if (l.tile_x > 2 * c->p.nx && l.tile_x > 32) continue;  // mostly idle lanes
+        if (c->mrt.on && !tile_has_mrt(ti)) continue;
         for (int zc : zcs) {
             if (zc > c->p.nz && zc != zcs[0]) break;
             l.zchunk = zc;
@@ -1067,6 +1146,7 @@ hipError_t batch_upload(lbm_batch *b) {
         A.G = b->p[i].G;
         A.rho0 = b->p[i].rho0;
         A.rho_ref = is_shifted(b->p[i].storage) ? b->p[i].rho_ref : 0.0;
+        A.mrt = MrtParams{};  // the batched form uses BGK
         cases[i].args = A;
         cases[i].lat[0] = case_lat(b, i, 0);
         cases[i].lat[1] = case_lat(b, i, 1);

@@ -141,6 +141,139 @@ __device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
     f[0] = rho - moving;
 }
 
+// ---------------------------------------------------------------------------
+// Multiple-relaxation-time collision, the operator the paper's conclusion
+// names as the next step (it lets the viscosity change at a fixed density
+// ratio).  Moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand and Luo
+// (2002) for D3Q19; row k of M is the polynomial of c defining moment k:
+//   rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz,
+//   pxz, mx, my, mz.
+// The rows are orthogonal, so M^-1 = M^T diag(1 / |row k|^2).  The equilibrium
+// moments are those of the second-order equilibrium of Eq. (2), so equal
+// rates reproduce BGK.  The force enters as the velocity shift of Eq. (6)
+// carried to moment space: the equilibrium is taken at j' = j + F / s_j, so
+// a collision adds exactly F to the momentum (s_j = 1/tau is BGK's shift).
+__host__ __device__ constexpr int mrt_row(int k, int a) {
+    const int x = kCX[a], y = kCY[a], z = kCZ[a];
+    const int c2 = x * x + y * y + z * z;
+    switch (k) {
+        case 0: return 1;
+        case 1: return 19 * c2 - 30;
+        case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+        case 3: return x;
+        case 4: return (5 * c2 - 9) * x;
+        case 5: return y;
+        case 6: return (5 * c2 - 9) * y;
+        case 7: return z;
+        case 8: return (5 * c2 - 9) * z;
+        case 9: return 3 * x * x - c2;
+        case 10: return (3 * c2 - 5) * (3 * x * x - c2);
+        case 11: return y * y - z * z;
+        case 12: return (3 * c2 - 5) * (y * y - z * z);
+        case 13: return x * y;
+        case 14: return y * z;
+        case 15: return x * z;
+        case 16: return (y * y - z * z) * x;
+        case 17: return (z * z - x * x) * y;
+        default: return (x * x - y * y) * z;
+    }
+}
+
+__host__ __device__ constexpr int mrt_norm2(int k) {
+    int s = 0;
+    for (int a = 0; a < Q; ++a) s += mrt_row(k, a) * mrt_row(k, a);
+    return s;
+}
+
+// Sum over a of mrt_row(k, a) * v[a] with the integer coefficients folded
+// at compile time (k, a are constants after unrolling).
+template <typename C>
+__device__ inline C mrt_moment(int k, const C (&v)[Q]) {
+    C acc = C(0);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int c = mrt_row(k, a);
+        if (c == 1) acc += v[a];
+        else if (c == -1) acc -= v[a];
+        else if (c != 0) acc += C(c) * v[a];
+    }
+    return acc;
+}
+
+// Rates of the moments: s[k] for moment k (s[0] unused), inv_sj = 1 / s_j.
+template <typename C>
+struct MrtRates {
+    C s[Q];
+    C inv_sj;
+};
+
+// Rates of every moment from the viscous rate omega = 1/tau and the other
+// rates (s_j <= 0 selects s_j = omega, the BGK velocity shift).
+template <typename C>
+__device__ inline MrtRates<C> mrt_rates(double omega, double s_e, double s_eps, double s_q, double s_pi,
+                                        double s_m, double s_j) {
+    const double sj = s_j > 0.0 ? s_j : omega;
+    const double v[Q] = {0.0, s_e, s_eps, sj, s_q, sj, s_q, sj, s_q, omega, s_pi, omega, s_pi,
+                         omega, omega, omega, s_m, s_m, s_m};
+    MrtRates<C> r;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) r.s[k] = C(v[k]);
+    r.inv_sj = C(1.0 / sj);
+    return r;
+}
+
+// MRT relaxation of f in place: m = M f, m* = m - S (m - m^eq(rho, j + F/s_j)),
+// f* = M^-1 m*, then the rest population from the exact mass (as in collide).
+template <typename C>
+__device__ inline void collide_mrt(C (&f)[Q], C Fx, C Fy, C Fz, const MrtRates<C> &r) {
+    C m[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) m[k] = mrt_moment(k, f);
+    const C rho = m[0], ir = C(1) / rho;
+    const C jx = m[3] + Fx * r.inv_sj, jy = m[5] + Fy * r.inv_sj, jz = m[7] + Fz * r.inv_sj;
+    const C jj = jx * jx + jy * jy + jz * jz;
+    C meq[Q];
+    meq[0] = rho;
+    meq[1] = C(-11) * rho + C(19) * jj * ir;
+    meq[2] = C(3) * rho - C(5.5) * jj * ir;
+    meq[3] = jx;
+    meq[4] = C(-2.0 / 3.0) * jx;
+    meq[5] = jy;
+    meq[6] = C(-2.0 / 3.0) * jy;
+    meq[7] = jz;
+    meq[8] = C(-2.0 / 3.0) * jz;
+    meq[9] = (C(3) * jx * jx - jj) * ir;
+    meq[10] = C(-0.5) * meq[9];
+    meq[11] = (jy * jy - jz * jz) * ir;
+    meq[12] = C(-0.5) * meq[11];
+    meq[13] = jx * jy * ir;
+    meq[14] = jy * jz * ir;
+    meq[15] = jx * jz * ir;
+    meq[16] = meq[17] = meq[18] = C(0);
+    // relaxed moments divided by the squared row norms (rho is conserved)
+    C w[Q];
+    w[0] = rho * C(1.0 / mrt_norm2(0));
+#pragma unroll
+    for (int k = 1; k < Q; ++k) w[k] = (m[k] - r.s[k] * (m[k] - meq[k])) * C(1.0 / mrt_norm2(k));
+    // f*_a = sum_k M_ka w_k: column a of M, i.e. row a of M^T
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        C acc = C(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int c = mrt_row(k, a);
+            if (c == 1) acc += w[k];
+            else if (c == -1) acc -= w[k];
+            else if (c != 0) acc += C(c) * w[k];
+        }
+        f[a] = acc;
+    }
+    C moving = f[1];
+#pragma unroll
+    for (int a = 2; a < Q; ++a) moving += f[a];
+    f[0] = rho - moving;
+}
+
 __device__ inline int wrapi(int v, int n) {
     int r = v % n;
     return r < 0 ? r + n : r;

@@ -9,6 +9,14 @@
 
 namespace lbm {
 
+// Collision operator: BGK (on = 0) or MRT with the given rates of the
+// non-viscous moments (the viscous ones relax at 1/tau); s_j <= 0 means
+// s_j = 1/tau.
+struct MrtParams {
+    int on;
+    double s_e, s_eps, s_q, s_pi, s_m, s_j;
+};
+
 // Arguments of one fused step launch over one grid.
 struct StepArgs {
     const void *src;
@@ -22,6 +30,7 @@ struct StepArgs {
     int64_t pop_stride;
     int row_stride, plane_stride;
     double tau, G, rho0, rho_ref;
+    MrtParams mrt;
 };
 
 // One case of a batch: its step arguments (src/dst unset) and both lattices.
@@ -87,7 +96,10 @@ void dynamic_tile(int threads, int nx, int ny, int *tw, int *th);
 int num_tiles();
 void tile_shape(int i, int *tx, int *ty);
 int find_tile(int tx, int ty);
+// A.mrt.on selects the MRT kernel, compiled for the run-time tiles only
+// (tile_has_mrt).
 hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s);
+bool tile_has_mrt(int tile_index);
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
                              const int4 *items, int nitems, const int32_t *frozen, int parity,
                              hipStream_t s);
@@ -120,7 +132,7 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // out[0] = rho(n/2), out[1] = rho(0), out[2] = max |rho - rho_before| over
 // the chunk, out[3] = 1 if a non-finite density appeared.
 hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    double hi, double lo, int chunk, int init, double *out,
-                                    hipStream_t s);
+                                    const MrtParams &mrt, double hi, double lo, int chunk, int init,
+                                    double *out, hipStream_t s);
 
 }  // namespace lbm

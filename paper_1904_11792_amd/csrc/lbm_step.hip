@@ -34,7 +34,7 @@ namespace lbm {
 __host__ __device__ constexpr int dyn_window(int threads) { return threads == 512 ? 900 : 1600; }
 __host__ __device__ constexpr int dyn_width_cap(int threads) { return threads == 512 ? 128 : 256; }
 
-template <int ST, int TXS, int TYS>
+template <int ST, int TXS, int TYS, bool MRT>
 __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk) {
     using Tr = Storage<ST>;
     using T = typename Tr::T;
@@ -56,6 +56,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int64_t S = A.pop_stride;
     const C rho0 = C(A.rho0), inv_rho0 = C(1.0 / A.rho0);
     const C G = C(A.G), tau = C(A.tau), omega = C(1.0 / A.tau);
+    MrtRates<C> rates;
+    if constexpr (MRT)
+        rates = mrt_rates<C>(1.0 / A.tau, A.mrt.s_e, A.mrt.s_eps, A.mrt.s_q, A.mrt.s_pi, A.mrt.s_m, A.mrt.s_j);
     C shift[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) shift[a] = Tr::kShifted ? C(weight(a) * A.rho_ref) : C(0);
@@ -125,7 +128,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         };
         C Fx, Fy, Fz;
         sc_force<C>(W(s0, ly + 1, lx + 1), G, P, Fx, Fy, Fz);
-        collide<C>(f, Fx, Fy, Fz, tau, omega);
+        if constexpr (MRT)
+            collide_mrt<C>(f, Fx, Fy, Fz, rates);
+        else
+            collide<C>(f, Fx, Fy, Fz, tau, omega);
         const int o = zc * plane + Y[1] + X[1];
 #pragma unroll
         for (int a = 0; a < Q; ++a)
@@ -145,12 +151,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     }
 }
 
-template <int ST, int TX, int TY>
+template <int ST, int TX, int TY, bool MRT>
 __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step(StepArgs A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
-    step_tile<ST, TX, TY>(A, tile % A.tiles_x, tile / A.tiles_x, chunk);
+    step_tile<ST, TX, TY, MRT>(A, tile % A.tiles_x, tile / A.tiles_x, chunk);
 }
 
 // Batched form: one launch covers every case's work items.  Items are
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_batch(const BatchCas
     StepArgs A = bc.args;
     A.src = bc.lat[parity];
     A.dst = bc.lat[parity ^ 1];
-    step_tile<ST, TX, TY>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z);
+    step_tile<ST, TX, TY, false>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -178,22 +184,28 @@ struct TileEntry {
     int tx, ty;
     const void *fn[4];
     const void *batch_fn[4];
+    const void *mrt_fn[4];  // MRT collision: run-time tiles only
 };
 
-#define LBM_TILE(TXV, TYV)                                                                   \
-    {TXV, TYV,                                                                               \
-     {(const void *)k_step<kF64, TXV, TYV>, (const void *)k_step<kF32, TXV, TYV>,           \
-      (const void *)k_step<kF16S, TXV, TYV>, (const void *)k_step<kBF16S, TXV, TYV>},       \
-     {(const void *)k_step_batch<kF64, TXV, TYV>, (const void *)k_step_batch<kF32, TXV, TYV>, \
-      (const void *)k_step_batch<kF16S, TXV, TYV>,                                          \
-      (const void *)k_step_batch<kBF16S, TXV, TYV>}}
+#define LBM_TILE_FNS(TXV, TYV)                                                                      \
+    {(const void *)k_step<kF64, TXV, TYV, false>, (const void *)k_step<kF32, TXV, TYV, false>,     \
+     (const void *)k_step<kF16S, TXV, TYV, false>, (const void *)k_step<kBF16S, TXV, TYV, false>}, \
+    {(const void *)k_step_batch<kF64, TXV, TYV>, (const void *)k_step_batch<kF32, TXV, TYV>,        \
+     (const void *)k_step_batch<kF16S, TXV, TYV>, (const void *)k_step_batch<kBF16S, TXV, TYV>}
+#define LBM_TILE(TXV, TYV) {TXV, TYV, LBM_TILE_FNS(TXV, TYV), {nullptr, nullptr, nullptr, nullptr}}
+#define LBM_TILE_MRT(TXV, TYV)                                                                     \
+    {TXV, TYV, LBM_TILE_FNS(TXV, TYV),                                                             \
+     {(const void *)k_step<kF64, TXV, TYV, true>, (const void *)k_step<kF32, TXV, TYV, true>,      \
+      (const void *)k_step<kF16S, TXV, TYV, true>, (const void *)k_step<kBF16S, TXV, TYV, true>}}
 
 // Entries (0, 512) and (0, 1024) are the run-time shaped tiles.
 static const TileEntry kTiles[] = {
-    LBM_TILE(0, 512), LBM_TILE(0, 1024), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
+    LBM_TILE_MRT(0, 512), LBM_TILE_MRT(0, 1024), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
     LBM_TILE(64, 4), LBM_TILE(32, 16), LBM_TILE(32, 8), LBM_TILE(16, 16),
 };
 #undef LBM_TILE
+#undef LBM_TILE_MRT
+#undef LBM_TILE_FNS
 
 void dynamic_tile(int threads, int nx, int ny, int *tw, int *th) {
     const int cap = dyn_width_cap(threads);
@@ -216,13 +228,17 @@ int find_tile(int tx, int ty) {
     return -1;
 }
 
+bool tile_has_mrt(int tile_index) { return kTiles[tile_index].mrt_fn[0] != nullptr; }
+
 hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
+    const void *fn = A.mrt.on ? e.mrt_fn[storage] : e.fn[storage];
+    if (!fn) return hipErrorInvalidDeviceFunction;
     const int nblk = A.tiles_x * A.tiles_y * A.nchunks;
     StepArgs args = A;
     void *kargs[] = {&args};
     const int threads = e.tx ? e.tx * e.ty : e.ty;
-    return hipLaunchKernel(e.fn[storage], dim3(nblk), dim3(threads), kargs, 0, s);
+    return hipLaunchKernel(fn, dim3(nblk), dim3(threads), kargs, 0, s);
 }
 
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,

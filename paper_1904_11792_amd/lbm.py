@@ -69,6 +69,25 @@ class lbm_diag(ctypes.Structure):
                 "nonfinite": int(self.nonfinite)}
 
 
+class lbm_mrt(ctypes.Structure):
+    _fields_ = [("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+                ("s_pi", ctypes.c_double), ("s_m", ctypes.c_double), ("s_j", ctypes.c_double)]
+
+
+# Rates of the non-hydrodynamic moments suggested by d'Humieres et al. (2002).
+MRT_DEFAULT = {"s_e": 1.19, "s_eps": 1.4, "s_q": 1.2, "s_pi": 1.4, "s_m": 1.98, "s_j": 0.0}
+
+
+def make_mrt(**rates) -> lbm_mrt:
+    """MRT rates; missing ones from MRT_DEFAULT (s_j = 0 selects 1/tau)."""
+    r = dict(MRT_DEFAULT)
+    unknown = set(rates) - set(r)
+    if unknown:
+        raise ValueError(f"unknown MRT rates {sorted(unknown)}")
+    r.update(rates)
+    return lbm_mrt(*(float(r[k]) for k in ("s_e", "s_eps", "s_q", "s_pi", "s_m", "s_j")))
+
+
 class lbm_droplet(ctypes.Structure):
     _fields_ = [("volume", ctypes.c_int64), ("mass", ctypes.c_double), ("first_node", ctypes.c_int64)]
 
@@ -86,6 +105,8 @@ _SIGS = {
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_coexistence": (ctypes.c_int, [_d, _d, _i32, _d, _P(_d), _P(_d)]),
     "lbm_equal_area": (ctypes.c_int, [_d, _i32, _d, _P(_d), _P(_d)]),
+    "lbm_coexistence_mrt": (ctypes.c_int, [_d, _d, _P(lbm_mrt), _i32, _d, _P(_d), _P(_d)]),
+    "lbm_set_mrt": (ctypes.c_int, [_vp, _P(lbm_mrt)]),
     "lbm_init_ligament": (ctypes.c_int, [_vp, _P(lbm_ligament)]),
     "lbm_step": (ctypes.c_int, [_vp, _i64]),
     "lbm_get_fields": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _i32]),
@@ -158,10 +179,25 @@ def lbm_destroy(ctx) -> None:
     _check(_lib.lbm_destroy(ctx))
 
 
-def lbm_coexistence(G: float, tau: float, psi: int = LBM_PSI_EXP, rho0: float = 1.0):
+def lbm_coexistence(G: float, tau: float, psi: int = LBM_PSI_EXP, rho0: float = 1.0,
+                    mrt: dict | None = None):
+    """Flat-interface coexistence densities; mrt: None (BGK) or MRT rates (make_mrt keys)."""
     rl, rv = _d(), _d()
-    _check(_lib.lbm_coexistence(G, tau, psi, rho0, ctypes.byref(rl), ctypes.byref(rv)))
+    if mrt is None:
+        _check(_lib.lbm_coexistence(G, tau, psi, rho0, ctypes.byref(rl), ctypes.byref(rv)))
+    else:
+        m = make_mrt(**mrt)
+        _check(_lib.lbm_coexistence_mrt(G, tau, ctypes.byref(m), psi, rho0, ctypes.byref(rl),
+                                        ctypes.byref(rv)))
     return rl.value, rv.value
+
+
+def lbm_set_mrt(ctx, mrt: dict | None) -> None:
+    if mrt is None:
+        _check(_lib.lbm_set_mrt(ctx, None))
+    else:
+        m = make_mrt(**mrt)
+        _check(_lib.lbm_set_mrt(ctx, ctypes.byref(m)))
 
 
 def lbm_equal_area(G: float, psi: int = LBM_PSI_EXP, rho0: float = 1.0):
@@ -277,7 +313,7 @@ class Lattice:
     """One periodic grid behind an lbm_ctx; device memory from torch."""
 
     def __init__(self, nx, ny, nz, tau, G, rho0=1.0, storage="f32", rho_ref=0.0,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, mrt: dict | None = None):
         self.params = make_params(nx, ny, nz, tau, G, rho0, storage, rho_ref)
         nbytes = lbm_workspace_bytes(self.params)
         if nbytes == 0:
@@ -290,6 +326,12 @@ class Lattice:
                               _stream_handle(self.stream))
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
+        if mrt is not None:
+            lbm_set_mrt(self.ctx, mrt)
+
+    def set_mrt(self, mrt: dict | None) -> None:
+        """Select the collision: None for BGK, else MRT rates (make_mrt keys)."""
+        lbm_set_mrt(self.ctx, mrt)
 
     def close(self):
         if getattr(self, "ctx", None):

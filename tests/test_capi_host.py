@@ -86,6 +86,17 @@ def test_coexistence_rejects_subcritical_and_bad_tau(lbm):
     assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
 
 
+def test_mrt_rates_are_validated_before_device_work(lbm):
+    for bad in ({"s_e": 0.0}, {"s_q": 2.0}, {"s_m": float("nan")}, {"s_j": 2.5}):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_coexistence(-5.5, 1.0, mrt=bad)
+        assert e.value.status == lbm.LBM_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        lbm.make_mrt(s_x=1.0)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_set_mrt(None, {})
+
+
 def test_null_handles_are_rejected(lbm):
     with pytest.raises(lbm.LbmError):
         lbm.lbm_step(None, 1)
