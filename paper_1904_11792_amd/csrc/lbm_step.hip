@@ -119,11 +119,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         }
     };
 
+    // Odd chunks march towards -z.  Two neighbouring chunks then read the
+    // planes around their common boundary at the same time (both at their
+    // start or both at their end), so the second read tends to hit L2; with
+    // short chunks those boundary planes are a large part of the gathers
+    // (measured: +3% on narrow grids at z chunks of 8-32 on MI355X).
+    const int dir = (chunk & 1) ? -1 : 1;
+    const int zfirst = dir > 0 ? z0 : z0 + kend - 1;
+
+    // Window slots: (k + 3) & 3 the plane behind, k & 3 the current one,
+    // (k + 1) & 3 the plane ahead (in the marching direction).
     auto collide_store = [&](int k, C(&f)[Q]) {
-        const int zc = z0 + k;
+        const int zc = zfirst + dir * k;
         const int sm = (k + 3) & 3, s0 = k & 3, sp = (k + 1) & 3;
         auto P = [&](int dx, int dy, int dz) -> C {
-            const int s = dz < 0 ? sm : (dz > 0 ? sp : s0);
+            const int d = dz * dir;
+            const int s = d < 0 ? sm : (d > 0 ? sp : s0);
             return W(s, ly + 1 + dy, lx + 1 + dx);
         };
         C Fx, Fy, Fz;
@@ -139,11 +150,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     };
 
     C cur[Q], nxt[Q];
-    load_plane(wrapi(z0 - 1, nz), 3, nxt);
-    load_plane(z0, 0, cur);
+    load_plane(wrapi(zfirst - dir, nz), 3, nxt);
+    load_plane(zfirst, 0, cur);
     for (int k = 0; k < kend; ++k) {
-        const int zc = z0 + k;
-        load_plane(wrapi(zc + 1, nz), (k + 1) & 3, nxt);
+        const int zc = zfirst + dir * k;
+        load_plane(wrapi(zc + dir, nz), (k + 1) & 3, nxt);
         __syncthreads();
         if (active) collide_store(k, cur);
 #pragma unroll
