@@ -105,7 +105,7 @@ def cpu_baseline(spec, rho_l, rho_v, budget_s=12.0):
     t0 = time.perf_counter()
     f = oracle.run(f, 1, spec.tau, spec.G)  # calibration step (also pages the arrays in)
     t1 = time.perf_counter() - t0
-    steps = max(2, min(50, int(budget_s / max(t1, 1e-3))))
+    steps = max(2, min(400, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     f = oracle.run(f, steps, spec.tau, spec.G)
     el = time.perf_counter() - t0
