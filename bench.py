@@ -19,6 +19,9 @@ Studies (one JSON line each, not the benchmark line):
   --form precision    FP16/BF16 shifted storage against FP32/FP64
   --form convergence  t_b / t_cap against 1/R, FP32 and FP64
   --form paper        the paper's Table 1 sweep (G = -5.3, Oh = 0.1)
+  --form small        the small FP64 ligament and R = 8, 16 of the convergence
+                      series on the GPU and in the CPU oracle (MLUPS of both)
+  --collision mrt     the MRT collision (single form and --form paper)
   --sweep             every compiled tile shape and several z chunks
 """
 from __future__ import annotations
@@ -123,7 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
     ap.add_argument("--form", default="single",
-                    choices=["single", "batch", "precision", "convergence", "paper"])
+                    choices=["single", "batch", "precision", "convergence", "paper", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
                     help="mrt: the multiple-relaxation-time collision with the suggested rates "
@@ -166,6 +169,8 @@ def main():
         return study_convergence(args, lbm, workloads, stream)
     if args.form == "paper":
         return study_paper(args, lbm, workloads, stream)
+    if args.form == "small":
+        return study_small(args, lbm, workloads, stream)
 
     spec = workloads.LARGE_FP32
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
@@ -361,6 +366,74 @@ def study_convergence(args, lbm, workloads, stream):
             print(f"# {json.dumps(r)}", file=sys.stderr, flush=True)
     print(json.dumps({"study": "convergence", "G": G, "tau": tau, "rho_l": rho_l, "rho_v": rho_v,
                       "sigma": sigma, "laplace_intercept": icpt, "rows": rows}))
+
+
+def study_small(args, lbm, workloads, stream):
+    """The small FP64 ligament (32 x 32 x 64, 2000 steps) and the two smallest
+    grid-convergence cases run to break-up, each on the GPU and in the FP64
+    CPU oracle on all host threads: MLUPS of both, break-up time, droplets,
+    mass drift.  These grids live in the MI355X's 256 MB Infinity Cache, so
+    only their MLUPS are meaningful, not an HBM fraction."""
+    import torch
+
+    import oracle
+    from paper_1904_11792_amd import analysis
+
+    rows = []
+    cases = [(workloads.SMALL_FP64, 2000)]
+    rho_l, rho_v = lbm.lbm_coexistence(-5.5, 1.0)
+    sigma, _ = analysis.laplace_sigma(lbm, -5.5, 1.0, rho_l, rho_v)
+    for R in (8, 16):
+        spec = workloads.convergence(R)
+        cases.append((spec, int(12 * analysis.capillary_time(rho_l, R, sigma))))
+    for spec, steps in cases:
+        for storage in ("f64", "f32"):
+            print(f"# {spec.name} {storage}, {steps} steps", file=sys.stderr, flush=True)
+            r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, steps, every=1)
+            lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage, rho_ref=rho_v,
+                              stream=stream)
+            lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength, rho_l=rho_l,
+                              rho_v=rho_v)
+            lat.step(20)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(steps)
+            e1.record(stream)
+            e1.synchronize()
+            plain_ms = e0.elapsed_time(e1)
+            # the same steps replayed as captured graphs of 100 steps (launch-bound grids)
+            lat.set_graph_chunk(100)
+            lat.step(200)
+            e0.record(stream)
+            lat.step(steps // 100 * 100)
+            e1.record(stream)
+            e1.synchronize()
+            graph_ms = e0.elapsed_time(e1) / (steps // 100 * 100) * steps
+            # and with the autotuned launch shape, in graphs
+            launch, _ = lat.autotune(20)
+            lat.step(200)
+            e0.record(stream)
+            lat.step(steps // 100 * 100)
+            e1.record(stream)
+            e1.synchronize()
+            tuned_ms = e0.elapsed_time(e1) / (steps // 100 * 100) * steps
+            lat.close()
+            r.update({"case": spec.name, "storage": storage, "steps_timed": steps,
+                      "gpu_MLUPS": round(spec.n * steps / plain_ms / 1e3, 1),
+                      "gpu_MLUPS_graph": round(spec.n * steps / graph_ms / 1e3, 1),
+                      "gpu_MLUPS_tuned": round(spec.n * steps / tuned_ms / 1e3, 1),
+                      "tuned_launch": list(launch)})
+            rows.append(r)
+        f = oracle.init_ligament(spec.nx, spec.ny, spec.nz, R0=spec.R0, amp_rel=spec.amp_rel,
+                                 wavelength=spec.wavelength, rho_l=rho_l, rho_v=rho_v)
+        t0 = time.perf_counter()
+        oracle.run(f, steps, spec.tau, spec.G)
+        el = time.perf_counter() - t0
+        rows.append({"case": spec.name, "storage": "oracle f64", "steps_timed": steps,
+                     "oracle_MLUPS": round(spec.n * steps / el / 1e6, 1), "cores": oracle.num_threads(),
+                     "seconds": round(el, 2)})
+        print(f"# {json.dumps(rows[-3:])}", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "small_grids", "rho_l": rho_l, "rho_v": rho_v, "sigma": sigma, "rows": rows}))
 
 
 def study_paper(args, lbm, workloads, stream):

@@ -912,7 +912,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, doub
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const int zcs[] = {4, 8, 16, 32, 64, 128, 256};
+    const int zcs[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
     double best_t = INFINITY;
     lbm_launch bl = c->launch;
     const double nodes = double(c->p.nx) * c->p.ny * c->p.nz;

@@ -131,10 +131,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // (k + 1) & 3 the plane ahead (in the marching direction).
     auto collide_store = [&](int k, C(&f)[Q]) {
         const int zc = zfirst + dir * k;
-        const int sm = (k + 3) & 3, s0 = k & 3, sp = (k + 1) & 3;
+        const int behind = (k + 3) & 3, s0 = k & 3, ahead = (k + 1) & 3;
+        const int s_lo = dir > 0 ? behind : ahead, s_hi = dir > 0 ? ahead : behind;  // planes z-1, z+1
         auto P = [&](int dx, int dy, int dz) -> C {
-            const int d = dz * dir;
-            const int s = d < 0 ? sm : (d > 0 ? sp : s0);
+            const int s = dz < 0 ? s_lo : (dz > 0 ? s_hi : s0);
             return W(s, ly + 1 + dy, lx + 1 + dx);
         };
         C Fx, Fy, Fz;
