@@ -284,6 +284,11 @@ int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
  * height balanced over ny with at most tile_y nodes and 64 rows.
  * zchunk >= 1.  The FP64 kernel is slow with 1024 threads (its registers do
  * not fit), the other storages run fastest there on grids of nx >= 128.
+ * A new context starts on the shape cached by lbm_autotune for its grid, else
+ * on the default: the run-time tile of 1024 threads (512 for FP64 or
+ * nx < 128) and the z chunk that gives about 256 workgroups (at least 4
+ * planes on grids of 2^22 nodes or more, where the two extra psi planes of a
+ * chunk cost HBM traffic; smaller grids live in the caches).
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

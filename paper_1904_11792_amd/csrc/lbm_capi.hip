@@ -194,7 +194,13 @@ lbm_launch default_launch(const lbm_params *p) {
     const int64_t tiles = int64_t((p->nx + tw - 1) / tw) * ((p->ny + th - 1) / th);
     int64_t chunks = (256 + tiles - 1) / tiles;
     int64_t zc = (p->nz + chunks - 1) / chunks;
-    if (zc < 4) zc = 4;
+    // A z chunk re-gathers two extra planes for psi.  On grids that live in
+    // HBM keep chunks of at least 4 planes; small grids live in the caches,
+    // where more workgroups pay more than the extra gathers cost (32x32x64 on
+    // MI355X: 1.7x (FP32) and 1.9x (FP64) faster at chunks of 1 than of 4).
+    const int64_t n = int64_t(p->nx) * p->ny * p->nz;
+    const int64_t zmin = n >= (int64_t(1) << 22) ? 4 : 1;
+    if (zc < zmin) zc = zmin;
     if (zc > p->nz) zc = p->nz;
     l.zchunk = int(zc);
     return l;
