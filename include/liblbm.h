@@ -351,6 +351,15 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
  * whole batch.
  */
 int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs);
+/*
+ * Advance every case by nsteps (stream-ordered).  Divergence checks run every
+ * 1000 steps on the device; the host takes in the flags of a check when the
+ * next one is enqueued (waiting for the device to reach it, so the host runs
+ * at most one check interval ahead) or at lbm_batch_diagnostics, and from
+ * then on launches no workgroups for the cases found frozen (their
+ * workgroups would only exit; measured 19% of a step for 13 frozen cases of
+ * 64).  Rebuilding the launch list synchronises the stream once.
+ */
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Per-case diagnostics (synchronises); frozen cases report nonfinite > 0. */
 int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out);

@@ -1017,6 +1017,13 @@ struct lbm_batch {
     hipGraphExec_t gexec;
     lbm_launch graph_launch;
     int graph_parity;
+    // Frozen cases are dropped from the item list once the host has seen
+    // their flags: h_frozen (pinned) receives a copy after each check,
+    // ev_frozen marks its arrival, dropped[i] = case i has no items.
+    int32_t *h_frozen;
+    hipEvent_t ev_frozen;
+    bool frozen_pending;
+    std::vector<uint8_t> dropped;
 };
 
 namespace {
@@ -1156,6 +1163,7 @@ hipError_t batch_upload(lbm_batch *b) {
         cases[i].args = A;
         cases[i].lat[0] = case_lat(b, i, 0);
         cases[i].lat[1] = case_lat(b, i, 1);
+        if (b->dropped[i]) continue;  // frozen: its workgroups would only exit
         // chunk-major, tile fastest: consecutive items are x-y neighbours of one case
         for (int c = 0; c < A.nchunks; ++c)
             for (int t = 0; t < A.tiles_x * A.tiles_y; ++t) items.push_back(make_int4(i, t, c, 0));
@@ -1182,9 +1190,11 @@ hipError_t batch_check_divergence(lbm_batch *b, DiagRecord *records) {
 
 hipError_t batch_plain(lbm_batch *b, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
-                                         b->d_frozen, b->parity, b->stream);
-        if (e != hipSuccess) return e;
+        if (b->nitems > 0) {  // no items: every case is frozen
+            hipError_t e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
+                                             b->d_frozen, b->parity, b->stream);
+            if (e != hipSuccess) return e;
+        }
         b->parity ^= 1;
         b->step += 1;
     }
@@ -1211,6 +1221,37 @@ hipError_t batch_build_graph(lbm_batch *b) {
     if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     b->graph_launch = b->launch;
+    return e;
+}
+
+// Drop the cases the last copied flags show frozen from the item list (the
+// upload synchronises the stream; it happens once per newly frozen set).
+hipError_t batch_compact(lbm_batch *b) {
+    b->frozen_pending = false;
+    bool changed = false;
+    for (int i = 0; i < b->n; ++i)
+        if (b->h_frozen[i] != 0 && !b->dropped[i]) {
+            b->dropped[i] = 1;
+            changed = true;
+        }
+    if (!changed) return hipSuccess;
+    batch_release_graph(b);
+    return batch_upload(b);
+}
+
+// After a divergence check has been enqueued: take in the flags of the
+// previous check (waiting for the device to reach it, so the host runs at
+// most one check interval ahead), then queue the copy of the new flags.
+hipError_t batch_after_check(lbm_batch *b) {
+    hipError_t e = hipSuccess;
+    if (b->frozen_pending) {
+        e = hipEventSynchronize(b->ev_frozen);
+        if (e == hipSuccess) e = batch_compact(b);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_frozen, b->d_frozen, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_frozen, b->stream);
+    if (e == hipSuccess) b->frozen_pending = true;
     return e;
 }
 
@@ -1269,9 +1310,18 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
     b->gexec = nullptr;
     b->launch = batch_default_launch(ncases, p);
     b->tile_index = find_tile(b->launch.tile_x, b->launch.tile_y);
-    hipError_t e = launch_fill_u64(b->d_slices, B.max_slices, 0ull, b->stream);
+    b->h_frozen = nullptr;
+    b->ev_frozen = nullptr;
+    b->frozen_pending = false;
+    b->dropped.assign(ncases, 0);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&b->h_frozen), sizeof(int32_t) * ncases,
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_frozen, hipEventDisableTiming);
+    if (e == hipSuccess) e = launch_fill_u64(b->d_slices, B.max_slices, 0ull, b->stream);
     if (e == hipSuccess) e = batch_upload(b);
     if (e != hipSuccess) {
+        if (b->ev_frozen) (void)hipEventDestroy(b->ev_frozen);
+        if (b->h_frozen) (void)hipHostFree(b->h_frozen);
         delete b;
         return fail(LBM_ERR_DEVICE, "lbm_batch_create: %s", hipGetErrorString(e));
     }
@@ -1282,6 +1332,8 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
 int lbm_batch_destroy(lbm_batch *b) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
     batch_release_graph(b);
+    if (b->ev_frozen) (void)hipEventDestroy(b->ev_frozen);
+    if (b->h_frozen) (void)hipHostFree(b->h_frozen);
     delete b;
     return LBM_OK;
 }
@@ -1326,6 +1378,13 @@ int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs) {
     e = hipMemcpyAsync(b->d_frozen, flags.data(), sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream);
     for (int i = 0; i < b->n && e == hipSuccess; ++i) e = launch_init_ligament(batch_ref(b, i, 0), args[i], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) {
+        // a new state: item lists of every case, minus those frozen from the start
+        b->frozen_pending = false;
+        for (int i = 0; i < b->n; ++i) b->dropped[i] = uint8_t(flags[i] != 0);
+        batch_release_graph(b);
+        e = batch_upload(b);
+    }
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_init");
     b->parity = 0;
     b->step = 0;
@@ -1340,13 +1399,18 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
     hipError_t e = hipSuccess;
+    if (b->frozen_pending) {  // flags of the last check already here: drop frozen cases now
+        const hipError_t q = hipEventQuery(b->ev_frozen);
+        if (q == hipSuccess) e = batch_compact(b);
+        else if (q != hipErrorNotReady) e = q;
+    }
     int64_t left = nsteps;
     while (e == hipSuccess && left > 0) {
         // run up to the next divergence check
         int64_t run = b->check_every - b->since_check;
         if (run > left) run = left;
         int64_t r = run;
-        if (b->graph_chunk > 0 && r >= b->graph_chunk) {
+        if (b->graph_chunk > 0 && r >= b->graph_chunk && b->nitems > 0) {
             if (b->parity == 1) {
                 e = batch_plain(b, 1);
                 r -= 1;
@@ -1364,6 +1428,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
         b->since_check += run;
         if (e == hipSuccess && b->since_check >= b->check_every) {
             e = batch_check_divergence(b, b->d_records);
+            if (e == hipSuccess) e = batch_after_check(b);
             b->since_check = 0;
         }
     }
@@ -1380,7 +1445,10 @@ int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out) {
     hipError_t e = batch_check_divergence(b, b->d_records);
     if (e == hipSuccess)
         e = hipMemcpyAsync(rec.data(), b->d_records, sizeof(DiagRecord) * b->n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_frozen, b->d_frozen, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = batch_compact(b);
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_diagnostics");
     for (int i = 0; i < b->n; ++i) to_public(rec[i], &out[i]);
     return LBM_OK;

@@ -112,6 +112,41 @@ def test_batch_freezes_diverged_case(lbm):
     torch.cuda.synchronize()
 
 
+def test_dropping_frozen_cases_leaves_live_ones_bitwise(lbm):
+    """Frozen cases leave the launch list once the host has seen them (at the
+    next check or at diagnostics); the live cases must evolve exactly as in a
+    batch that never held the frozen one, across several checks, with and
+    without graphs."""
+    import torch
+
+    cases = workloads.batch64(seed=11, count=3)
+    stable = [lbm.make_params(cases[i].nx, cases[i].ny, cases[i].nz, 1.0, -5.5, storage="f32") for i in (0, 2)]
+    bad = lbm.make_params(cases[1].nx, cases[1].ny, cases[1].nz, 0.5001, -7.5, storage="f32")
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
+                               rho_l=2.3, rho_v=0.1, seed=c.seed) for c in cases]
+    st = torch.cuda.Stream()  # graph capture needs a stream of its own
+    a = lbm.Batch([stable[0], bad, stable[1]], stream=st)
+    a.init(specs)
+    ref = lbm.Batch(stable, stream=st)
+    ref.init([specs[0], specs[2]])
+    for bt in (a, ref):
+        bt.set_launch(0, 512, 8)
+        bt.set_graph_chunk(100)
+    a.step(1100)  # first check at 1000 freezes case 1 on the device
+    ref.step(1100)
+    a.step(1500)  # the check at 2000 takes in the flags of 1000: case 1 leaves the launch
+    ref.step(1500)
+    a.step(7)  # odd step count: plain launches after the graphs
+    ref.step(7)
+    d = a.diagnostics()
+    assert d[1]["nonfinite"] > 0 and d[0]["nonfinite"] == 0 and d[2]["nonfinite"] == 0
+    for i, j in ((0, 0), (2, 1)):
+        pa = a.fields(i, rho=False, pop=True)["pop"].cpu().numpy()
+        pr = ref.fields(j, rho=False, pop=True)["pop"].cpu().numpy()
+        assert np.array_equal(pa, pr), i
+    torch.cuda.synchronize()
+
+
 def test_diag_ring_keeps_last_records(lbm):
     lat = lbm.Lattice(8, 8, 8, 0.9, -5.0, storage="f32")
     lat.set_populations(workloads.random_populations((8, 8, 8), seed=4))
