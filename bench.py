@@ -151,7 +151,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU z-slab "
-              "decomposition is a design, not part of this build.", file=sys.stderr)
+              "decomposition is a design only; it is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

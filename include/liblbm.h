@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
     LBM_OK = 0,
     LBM_ERR_INVALID_ARG = -1,    /* bad argument; nothing changed */
-    LBM_ERR_UNSUPPORTED = -2,    /* valid request this build does not provide */
+    LBM_ERR_UNSUPPORTED = -2,    /* valid request the library does not provide */
     LBM_ERR_DEVICE = -3,         /* a HIP call failed; the context is poisoned */
     LBM_ERR_STATE = -4,          /* call on a poisoned or uninitialised object */
     LBM_ERR_DIVERGED = -5,       /* non-finite or non-positive density found */

@@ -66,8 +66,9 @@ def sc94_construction(G):
 
 
 def test_sc94_construction_reference_values(oracle_mod):
-    """The construction itself, at G = -5.5 (values from the survey-time probe),
-    and the oracle's bracketing implementation against this test's fsolve one."""
+    """The construction itself at G = -5.5 against values computed beforehand
+    with a separate numpy solver (2.30752 / 0.10481), and the oracle's
+    bracketing implementation against this test's fsolve one."""
     rl, rv = sc94_construction(-5.5)
     assert rl == pytest.approx(2.30752, abs=2e-5)
     assert rv == pytest.approx(0.10481, abs=2e-5)
