@@ -412,13 +412,13 @@ def droplets(rho: np.ndarray, rho_mid: float):
 
 
 def run_to_breakup(f: np.ndarray, tau: float, G: float, rho_mid: float, max_steps: int,
-                   every: int = 1, rho0: float = 1.0, axis: int = 2):
+                   every: int = 1, rho0: float = 1.0, axis: int = 2, mrt: dict | None = None):
     """Step the oracle, sampling the neck density every `every` steps, until it
     falls below rho_mid or max_steps.  Returns (t_b or None, steps, necks, f)."""
     steps, necks = [0], [diag(f, axis)["neck_rho"]]
     t = 0
     while t < max_steps and necks[-1] >= rho_mid:
-        f = run(f, every, tau, G, rho0)
+        f = run(f, every, tau, G, rho0, mrt)
         t += every
         steps.append(t)
         necks.append(diag(f, axis)["neck_rho"])

@@ -161,3 +161,33 @@ def test_mass_conserved_over_1000_steps(lbm):
     lat.close()
     assert d["nonfinite"] == 0
     assert d["mass"] == pytest.approx(m0, rel=1e-13)
+
+
+def test_small_ligament_breakup_parity(lbm, oracle_mod):
+    """Long run with the MRT collision on the small ligament (32 x 32 x 64,
+    tau 1, G -5.5, suggested ghost rates, s_j = 1): break-up time within 1%
+    of the oracle's, then at step 1500 the same droplets and total mass."""
+    from paper_1904_11792_amd import analysis
+
+    s = workloads.SMALL_FP64
+    mrt = dict(DH, s_j=1.0)
+    co = oracle_mod.coexistence(s.G, s.tau, mrt=mrt)
+    mid = 0.5 * (co.rho_l + co.rho_v)
+    spec = dict(R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength, rho_l=co.rho_l, rho_v=co.rho_v)
+    f0 = oracle_mod.init_ligament(s.nx, s.ny, s.nz, **spec)
+    tb_ref, steps, _, f = oracle_mod.run_to_breakup(f0, s.tau, s.G, mid, 1500, mrt=mrt)
+    f = oracle_mod.run(f, 1500 - steps[-1], s.tau, s.G, mrt=mrt)
+    count, vols, _ = oracle_mod.droplets(f.sum(axis=0), mid)
+    assert tb_ref is not None
+    for storage in ("f64", "f32"):
+        lat = lbm.Lattice(s.nx, s.ny, s.nz, s.tau, s.G, storage=storage, mrt=mrt)
+        lat.init_ligament(**spec)
+        tb, _, _, _ = analysis.run_to_breakup(lat, co.rho_l, co.rho_v, 1500, every=1)
+        print(f"MRT {storage}: break-up {tb} (oracle {tb_ref})")
+        assert tb == pytest.approx(tb_ref, rel=0.01)
+        lat.step(1500 - lat.step_count)
+        d = lat.droplets(mid)
+        assert d["count"] == count and np.allclose(d["volumes"], vols, rtol=0.01)
+        m = lat.diagnostics()["mass"]
+        assert m == pytest.approx(oracle_mod.diag(f)["mass"], rel=1e-12 if storage == "f64" else 1e-5)
+        lat.close()
