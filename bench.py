@@ -23,6 +23,8 @@ Studies (one JSON line each, not the benchmark line):
                       series on the GPU and in the CPU oracle (MLUPS of both)
   --collision mrt     the MRT collision (single form and --form paper)
   --sweep             every compiled tile shape and several z chunks
+  --slab N            the single form on the first N z planes (one GPU's share
+                      of a z-slab decomposition, without the exchange)
 """
 from __future__ import annotations
 
@@ -134,6 +136,9 @@ def main():
                          "of d'Humieres et al. and s_j = 1/tau")
     ap.add_argument("--graph-chunk", type=int, default=0)
     ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
+    ap.add_argument("--slab", type=int, default=0,
+                    help="run the large ligament's first SLAB z planes only (one GPU's share of a "
+                         "z-slab decomposition; periodic in z, no halo exchange)")
     ap.add_argument("--sweep", action="store_true",
                     help="time every compiled tile and a set of z chunks, print a markdown table")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -174,6 +179,10 @@ def main():
         return study_small(args, lbm, workloads, stream)
 
     spec = workloads.LARGE_FP32
+    if args.slab:
+        import dataclasses
+
+        spec = dataclasses.replace(spec, name=f"large_fp32 slab 256x256x{args.slab}", nz=args.slab)
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
     rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
     mrt = {} if args.collision == "mrt" else None
