@@ -25,6 +25,7 @@ Studies (one JSON line each, not the benchmark line):
   --sweep             every compiled tile shape and several z chunks
   --slab N            the single form on the first N z planes (one GPU's share
                       of a z-slab decomposition, without the exchange)
+  --grid NX,NY,NZ     the single form on another grid, up to 2^31 - 1 nodes
 """
 from __future__ import annotations
 
@@ -139,6 +140,9 @@ def main():
     ap.add_argument("--slab", type=int, default=0,
                     help="run the large ligament's first SLAB z planes only (one GPU's share of a "
                          "z-slab decomposition; periodic in z, no halo exchange)")
+    ap.add_argument("--grid", default="",
+                    help="NX,NY,NZ: the single form on another grid (same ligament, five waves along z; "
+                         "no CPU baseline), e.g. 1024,1024,1024 to fill most of the HBM")
     ap.add_argument("--sweep", action="store_true",
                     help="time every compiled tile and a set of z chunks, print a markdown table")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -183,6 +187,12 @@ def main():
         import dataclasses
 
         spec = dataclasses.replace(spec, name=f"large_fp32 slab 256x256x{args.slab}", nz=args.slab)
+    if args.grid:
+        import dataclasses
+
+        gx, gy, gz = [int(v) for v in args.grid.split(",")]
+        spec = dataclasses.replace(spec, name=f"large ligament {gx}x{gy}x{gz}", nx=gx, ny=gy, nz=gz,
+                                   wavelength=gz / 5.0)
     print(f"# workload {spec.name}, storage {args.storage}", file=sys.stderr, flush=True)
     rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
     mrt = {} if args.collision == "mrt" else None
@@ -200,8 +210,9 @@ def main():
         lat.set_graph_chunk(args.graph_chunk)
     launch = lat.get_launch()
 
-    # plain copy kernel of the same size as one lattice pass: practical HBM ceiling
-    nbytes = 19 * spec.n * BYTES_PER_POP[args.storage]
+    # plain copy kernel of the same size as one lattice pass (at most that of
+    # the 256x256x1024 grid): practical HBM ceiling
+    nbytes = 19 * min(spec.n, workloads.LARGE_FP32.n) * BYTES_PER_POP[args.storage]
     with torch.cuda.stream(stream):
         a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -246,7 +257,7 @@ def main():
     }
     print(f"# {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s",
           file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline and mrt is None:
+    if not args.no_cpu_baseline and mrt is None and not args.grid:
         out["cpu_baseline"] = cpu_baseline(spec, rho_l, rho_v)
     print(json.dumps(out), flush=True)
 

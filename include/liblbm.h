@@ -65,7 +65,7 @@ typedef enum { LBM_PSI_EXP = 0 } lbm_psi;
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
 
 typedef struct {
-    int32_t nx, ny, nz; /* grid extents, each >= 1, n = nx*ny*nz <= 2^31 / 19 */
+    int32_t nx, ny, nz; /* grid extents, each >= 1; 19 nx ny and n = nx ny nz <= 2^31 - 1 */
     double tau;         /* relaxation time, > 0.5 (Eq. 1) */
     double G;           /* interaction strength of Eq. (5), signed, finite */
     int32_t psi;        /* lbm_psi */

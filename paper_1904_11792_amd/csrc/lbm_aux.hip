@@ -514,9 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_union(int32_t *parent, int nx, in
 
 // Every foreground node points at its root.
 __global__ __launch_bounds__(kBlock) void k_cc_compress(int32_t *parent, int n) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
         if (cc_load(&parent[i]) >= 0)
-            __hip_atomic_store(&parent[i], cc_find(parent, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&parent[i], cc_find(parent, int(i)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Volume (nodes) and mass (sum of rho) per root.  The FP64 atomic sums make
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_compress(int32_t *parent, int n) 
 __global__ __launch_bounds__(kBlock) void k_cc_accumulate(const int32_t *__restrict__ parent,
                                                           const double *__restrict__ rho, int n,
                                                           int32_t *vol, double *mass) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
         const int r = parent[i];
         if (r >= 0) {
             atomicAdd(&vol[r], 1);
@@ -537,8 +537,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_accumulate(const int32_t *__restr
 __global__ __launch_bounds__(kBlock) void k_cc_count(const int32_t *__restrict__ vol, int n,
                                                      int32_t *counter) {
     const int lane = threadIdx.x & 63;
-    for (int base = (blockIdx.x * kBlock + threadIdx.x) & ~63; base < n; base += gridDim.x * kBlock) {
-        const int i = base + lane;
+    for (int64_t base = (blockIdx.x * int64_t(kBlock) + threadIdx.x) & ~int64_t(63); base < n;
+         base += int64_t(gridDim.x) * kBlock) {
+        const int64_t i = base + lane;
         const unsigned long long m = __ballot(i < n && vol[i] > 0);
         if (lane == 0 && m) atomicAdd(counter, int32_t(__popcll(m)));
     }
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_count(const int32_t *__restrict__
 __global__ __launch_bounds__(kBlock) void k_cc_write(const int32_t *__restrict__ vol,
                                                      const double *__restrict__ mass, int n,
                                                      int32_t *counter, DropletEntry *out, int cap) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
         const int v = vol[i];
         if (v > 0) {
             const int k = atomicAdd(counter, 1);

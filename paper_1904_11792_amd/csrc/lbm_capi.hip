@@ -49,10 +49,12 @@ int validate_params(const lbm_params *p) {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    // Offsets within a z plane (19 nx ny populations) and node indices are 32-bit.
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    if (n * Q > int64_t(0x7fffffff))
-        return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes is too large for 32-bit site offsets",
-                    (long long)n);
+    if (int64_t(Q) * p->nx * p->ny > int64_t(0x7fffffff))
+        return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane holds more than 2^31 - 1 populations", p->nx, p->ny);
+    if (n > int64_t(0x7fffffff))
+        return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1 nodes", (long long)n);
     if (!(p->tau > 0.5) || !isfinite(p->tau))
         return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 0.5 (got %g)", p->tau);
     if (!isfinite(p->G)) return fail(LBM_ERR_INVALID_ARG, "G must be finite");

@@ -26,7 +26,7 @@ struct StepArgs {
     int tile_w, tile_h;  // tile shape (used by the run-time shaped kernel)
     // element offset of population a at node (x, y, z):
     //   a * pop_stride + z * plane_stride + y * row_stride + x
-    // (the node part, z * plane_stride + y * row_stride + x, fits in 32 bits)
+    // (the part within a plane, y * row_stride + x + a * pop_stride, fits in 32 bits)
     int64_t pop_stride;
     int row_stride, plane_stride;
     double tau, G, rho0, rho_ref;

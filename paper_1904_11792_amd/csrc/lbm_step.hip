@@ -50,10 +50,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     auto W = [&](int s, int yy, int xx) -> C & { return win[s * WIN + yy * PX + xx]; };
 
     const int nx = A.nx, ny = A.ny, nz = A.nz;
-    const int plane = A.plane_stride, rowst = A.row_stride;
+    const int64_t plane = A.plane_stride;
+    const int rowst = A.row_stride;
     const T *__restrict__ src = static_cast<const T *>(A.src);
     T *__restrict__ dst = static_cast<T *>(A.dst);
-    const int64_t S = A.pop_stride;
+    const int S = int(A.pop_stride);
     const C rho0 = C(A.rho0), inv_rho0 = C(1.0 / A.rho0);
     const C G = C(A.G), tau = C(A.tau), omega = C(1.0 / A.tau);
     MrtRates<C> rates;
@@ -98,13 +99,23 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int RX[3] = {wrapi(rgx - 1, nx), rgx, wrapi(rgx + 1, nx)};
     const int RY[3] = {wrapi(rgy - 1, ny) * rowst, rgy * rowst, wrapi(rgy + 1, ny) * rowst};
 
+    // The plane offset is 64-bit and wave-uniform; the offset within a plane
+    // is 32-bit (the host keeps 19 nx ny below 2^31).
     auto gather = [&](int zc, const int(&XX)[3], const int(&YY)[3], C(&f)[Q]) {
-        const int Z[3] = {wrapi(zc - 1, nz) * plane, zc * plane, wrapi(zc + 1, nz) * plane};
+        const T *Zp[3] = {src + wrapi(zc - 1, nz) * plane, src + zc * plane, src + wrapi(zc + 1, nz) * plane};
+        // Opaque copies of the row offsets: without them the compiler keeps
+        // 19 loop-invariant 64-bit addresses per thread (38 VGPRs) across the
+        // march instead of forming each address at its load.
+        int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
+        asm volatile("" : "+v"(yy[0]), "+v"(yy[1]), "+v"(yy[2]), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]));
+        // All 19 loads are issued before the first use: the scheduler would
+        // otherwise interleave load, wait and convert for 16-bit storage.
+        T raw[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const int off = Z[1 - kCZ[a]] + YY[1 - kCY[a]] + XX[1 - kCX[a]];
-            f[a] = Tr::decode(src[a * S + off], shift[a]);
-        }
+        for (int a = 0; a < Q; ++a) raw[a] = (Zp[1 - kCZ[a]] + a * S)[yy[1 - kCY[a]] + xx[1 - kCX[a]]];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[a] = Tr::decode(raw[a], shift[a]);
     };
     // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
     auto load_plane = [&](int zc, int s, C(&f)[Q]) {
@@ -143,10 +154,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
             collide_mrt<C>(f, Fx, Fy, Fz, rates);
         else
             collide<C>(f, Fx, Fy, Fz, tau, omega);
-        const int o = zc * plane + Y[1] + X[1];
+        T *const zb = dst + zc * plane;
+        int o = Y[1] + X[1];
+        asm volatile("" : "+v"(o));  // as in gather: form each store address here
 #pragma unroll
         for (int a = 0; a < Q; ++a)
-            __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), &dst[a * S + o]);
+            __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), &(zb + a * S)[o]);
     };
 
     C cur[Q], nxt[Q];

@@ -50,10 +50,15 @@ def test_workspace_bytes_and_validation(lbm):
     bad = [lbm.make_params(0, 4, 4, 0.8, -5.5), lbm.make_params(4, 4, 4, 0.5, -5.5),
            lbm.make_params(4, 4, 4, float("nan"), -5.5), lbm.make_params(4, 4, 4, 0.8, float("inf")),
            lbm.make_params(4, 4, 4, 0.8, -5.5, rho0=0.0), lbm.make_params(4, 4, 4, 0.8, -5.5, storage=7),
-           lbm.make_params(2048, 2048, 1024, 0.8, -5.5)]
+           lbm.make_params(2048, 2048, 1024, 0.8, -5.5),   # 2^32 nodes
+           lbm.make_params(1024, 1024, 2048, 0.8, -5.5),   # 2^31 nodes, one more than node indices allow
+           lbm.make_params(11000, 11000, 1, 0.8, -5.5)]    # 19 nx ny > 2^31 - 1 in one plane
     for q in bad:
         assert lbm.lbm_workspace_bytes(q) == 0
         assert lbm.lbm_last_error() != ""
+    # Offsets are 64-bit across planes: grids of more than 2^31 populations are fine.
+    big = lbm.make_params(1024, 1024, 1024, 0.8, -5.5, storage="f32")
+    assert lbm.lbm_workspace_bytes(big) >= 2 * 19 * 4 * 1024**3
 
 
 def test_create_rejects_bad_arguments_before_device_work(lbm):
