@@ -475,9 +475,12 @@ def study_paper(args, lbm, workloads, stream):
     if args.collision == "mrt":
         return study_paper_mrt(args, lbm, workloads, stream, analysis)
     rows = []
-    for R0, rl_p, rv_p, sg_p in workloads.TABLE1:
-        spec = workloads.paper_table1(R0)
-        rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+    specs = [workloads.paper_table1(row[0]) for row in workloads.TABLE1]
+    co_l, co_v, co_st = lbm.lbm_coexistence_many([s.G for s in specs], [s.tau for s in specs])
+    if (co_st != lbm.LBM_OK).any():
+        raise RuntimeError(f"flat-interface run diverged for R0 = {[r[0] for r, s in zip(workloads.TABLE1, co_st) if s]}")
+    for (R0, rl_p, rv_p, sg_p), spec, rho_l, rho_v in zip(workloads.TABLE1, specs, co_l, co_v):
+        rho_l, rho_v = float(rho_l), float(rho_v)
         try:
             sigma, icpt = analysis.laplace_sigma(lbm, spec.G, spec.tau, rho_l, rho_v, width=4.0)
         except RuntimeError as exc:

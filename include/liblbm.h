@@ -145,6 +145,23 @@ int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, d
                         double *rho_l, double *rho_v);
 
 /*
+ * lbm_coexistence for m (G, tau) pairs at once: the m flat-interface runs
+ * (each as described for lbm_coexistence, with the same stages and stopping
+ * rule, hence the same densities) advance together, one workgroup each, so m
+ * runs take about as long as the slowest one.  mrt: NULL for BGK, else the
+ * MRT rates shared by all runs.  Outputs are host arrays of m entries:
+ * status[j] is LBM_OK or LBM_ERR_DIVERGED, and a diverged run's densities
+ * are NaN.  Returns LBM_OK if every run converged, LBM_ERR_DIVERGED if any
+ * diverged (the others' results are valid).  Synchronous.  Errors before any
+ * device work: INVALID_ARG (m < 1, a NULL array, any case's G or tau invalid
+ * as for lbm_coexistence; the message names the case), UNSUPPORTED (psi);
+ * then DEVICE.
+ */
+int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt,
+                         int32_t psi, double rho0, double *rho_l, double *rho_v,
+                         int32_t *status);
+
+/*
  * Select the collision of a context: mrt = NULL for BGK (the default), else
  * the MRT rates above (copied).  The MRT kernels are compiled for the
  * run-time tiles (tile_x = 0); if the current launch uses a compile-time
@@ -345,8 +362,9 @@ size_t lbm_batch_workspace_bytes(int32_t ncases, const lbm_params *p);
 int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, size_t ws_bytes,
                      void *hip_stream, lbm_batch **out);
 /*
- * Set up every case (lbm_init_ligament semantics).  A case whose densities
- * are to come from lbm_coexistence but whose flat interface diverges at its
+ * Set up every case (lbm_init_ligament semantics).  The cases whose
+ * densities are to come from lbm_coexistence get them from one
+ * lbm_coexistence_many run.  A case whose flat interface diverges at its
  * (G, tau) starts frozen with non-finite densities instead of failing the
  * whole batch.
  */

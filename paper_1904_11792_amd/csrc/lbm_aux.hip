@@ -334,10 +334,14 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy16(u32x4 *__restrict__ dst, 
 // thread per node.  The x and y neighbours of a node are the node itself,
 // so the same force stencil and collision as the 3-D step apply unchanged.
 // State convention here: f_a(z, t) at z (push streaming inside LDS).
-__global__ __launch_bounds__(1024) void k_coexistence(double *__restrict__ state, int n, double G,
-                                                      double tau, double rho0, MrtParams mrt, double hi,
-                                                      double lo, int chunk, int init,
-                                                      double *__restrict__ out) {
+// One workgroup per flat-interface run: case blockIdx.x of the table.
+__global__ __launch_bounds__(1024) void k_coexistence(const CoexCase *__restrict__ cases, int n, int chunk) {
+    const CoexCase &cc = cases[blockIdx.x];
+    double *__restrict__ state = cc.state;
+    double *__restrict__ out = cc.out;
+    const double G = cc.G, tau = cc.tau, rho0 = cc.rho0, hi = cc.hi, lo = cc.lo;
+    const MrtParams mrt = cc.mrt;
+    const int init = cc.init;
     extern __shared__ double sm[];
     double *fa = sm;              // [19][n]
     double *fb = sm + Q * n;      // [19][n]
@@ -680,12 +684,9 @@ hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *o
     return hipGetLastError();
 }
 
-hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    const MrtParams &mrt, double hi, double lo, int chunk, int init,
-                                    double *out, hipStream_t s) {
+hipError_t launch_coexistence_chunk(const CoexCase *cases, int ncases, int n, int chunk, hipStream_t s) {
     const size_t lds = sizeof(double) * (2 * Q * n + 2 * n);
-    hipLaunchKernelGGL(k_coexistence, dim3(1), dim3(n), lds, s, state, n, G, tau, rho0, mrt, hi, lo, chunk,
-                       init, out);
+    hipLaunchKernelGGL(k_coexistence, dim3(ncases), dim3(n), lds, s, cases, n, chunk);
     return hipGetLastError();
 }
 

@@ -550,65 +550,59 @@ MrtParams mrt_params(const lbm_mrt *m) {
     return p;
 }
 
-int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, double rho0, double *rho_l,
-                     double *rho_v) {
-    if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
-    if (mrt_in) {
-        const int mst = check_mrt(mrt_in);
-        if (mst != LBM_OK) return mst;
-    }
-    const MrtParams mrt = mrt_params(mrt_in);
+int check_coexistence_args(double G, double tau, int32_t psi, double rho0) {
     if (psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", psi);
     if (!(tau > 0.5) || !isfinite(tau)) return fail(LBM_ERR_INVALID_ARG, "tau must be > 0.5");
     if (!(rho0 > 0.0) || !isfinite(rho0)) return fail(LBM_ERR_INVALID_ARG, "rho0 must be > 0");
     if (!(G < -4.0 / rho0) || !isfinite(G))
         return fail(LBM_ERR_INVALID_ARG, "no liquid-vapour coexistence for G = %g (needs G < %g)", G, -4.0 / rho0);
-    const int n = 128, chunk = 1000, max_chunks = 200;
-    double *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(double) * (Q * n + 4));
-    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
-    double start_l, start_v;
-    EqualArea{G, rho0}.solve(&start_l, &start_v);
-    // Relaxation stages for tau < 1: tau = 1, then lowered by 0.05 down to
-    // (excluding) the target, each until the chunk residual is below 1e-8 or
-    // 100 chunks.  Then the target tau with the full stopping rule.
+    return LBM_OK;
+}
+
+// Host side of one flat-interface run: the tau stages and the stopping rule.
+// Relaxation stages for tau < 1: tau = 1, then lowered by 0.05 down to
+// (excluding) the target, each until the chunk residual is below 1e-8 or 100
+// chunks.  Then the target tau until the residual is below 1e-12, until it has
+// grown 100-fold above its smallest value once that is below 1e-8, or for 200
+// chunks; the densities of the chunk with the smallest residual are the result.
+struct CoexRun {
+    static constexpr int kStageChunks = 100, kFinalChunks = 200;
+    double G, tau, rho0;
+    MrtParams mrt;
+    double start_l = 0, start_v = 0;
     std::vector<double> stages;
-    if (tau < 1.0)
-        for (int k = 0;; ++k) {
-            const double t = 1.0 - 0.05 * k;
-            if (!(t > tau + 1e-12)) break;
-            stages.push_back(t);
-        }
-    bool first = true;
-    double out[4];
-    auto run_chunk = [&](double t) -> hipError_t {
-        hipError_t err = launch_coexistence_chunk(d, n, G, t, rho0, mrt, start_l, start_v, chunk, first ? 1 : 0,
-                                                  d + Q * n, nullptr);
-        first = false;
-        if (err == hipSuccess) err = hipMemcpy(out, d + Q * n, sizeof(out), hipMemcpyDeviceToHost);
-        return err;
-    };
-    int st = LBM_OK;
-    bool diverged = false;
-    for (double t : stages) {
-        for (int k = 0; k < 100 && e == hipSuccess; ++k) {
-            e = run_chunk(t);
-            if (e != hipSuccess) break;
-            if (out[3] != 0.0) {
-                diverged = true;
-                break;
-            }
-            if (out[2] < 1e-8) break;
-        }
-        if (e != hipSuccess || diverged) break;
-    }
+    size_t stage = 0;  // == stages.size(): at the requested tau
+    int k = 0;         // chunks run in the current stage
+    bool first = true, done = false, diverged = false;
     double best = INFINITY, bl = 0, bv = 0;
-    for (int k = 0; k < max_chunks && e == hipSuccess && !diverged; ++k) {
-        e = run_chunk(tau);
-        if (e != hipSuccess) break;
+
+    CoexRun(double G_, double tau_, double rho0_, const MrtParams &m) : G(G_), tau(tau_), rho0(rho0_), mrt(m) {
+        EqualArea{G, rho0}.solve(&start_l, &start_v);
+        if (tau < 1.0)
+            for (int i = 0;; ++i) {
+                const double t = 1.0 - 0.05 * i;
+                if (!(t > tau + 1e-12)) break;
+                stages.push_back(t);
+            }
+    }
+    double current_tau() const { return stage < stages.size() ? stages[stage] : tau; }
+    // Takes the result of the chunk just run (out as in launch_coexistence_chunk).
+    void take(const double *out) {
+        first = false;
+        ++k;
+        if (stage < stages.size()) {
+            if (out[3] != 0.0) {
+                diverged = done = true;
+            } else if (out[2] < 1e-8 || k >= kStageChunks) {
+                ++stage;
+                k = 0;
+            }
+            return;
+        }
         if (out[3] != 0.0) {
             if (!(best < INFINITY)) diverged = true;
-            break;
+            done = true;
+            return;
         }
         const double res = out[2];
         if (res < best) {
@@ -616,14 +610,70 @@ int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, d
             bl = out[0];
             bv = out[1];
         }
-        if (res < 1e-12 || (best < 1e-8 && res > 100.0 * best)) break;
+        if (res < 1e-12 || (best < 1e-8 && res > 100.0 * best) || k >= kFinalChunks) done = true;
     }
-    (void)hipFree(d);
-    if (e != hipSuccess) st = fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
-    else if (diverged) st = fail(LBM_ERR_DIVERGED, "flat interface diverged for G=%g tau=%g", G, tau);
-    if (st != LBM_OK) return st;
-    *rho_l = bl;
-    *rho_v = bv;
+};
+
+// Advances every run to its end, all unfinished runs in one launch per chunk
+// (one workgroup each).  Synchronous.
+hipError_t run_coexistence(std::vector<CoexRun> &runs) {
+    const int n = 128, chunk = 1000;
+    const size_t m = runs.size();
+    double *d_state = nullptr, *d_out = nullptr;
+    CoexCase *d_cases = nullptr;
+    hipError_t e = hipMalloc(&d_state, sizeof(double) * Q * n * m);
+    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * 4 * m);
+    if (e == hipSuccess) e = hipMalloc(&d_cases, sizeof(CoexCase) * m);
+    std::vector<CoexCase> table;
+    std::vector<size_t> idx;
+    std::vector<double> outs(4 * m);
+    while (e == hipSuccess) {
+        table.clear();
+        idx.clear();
+        for (size_t j = 0; j < m; ++j) {
+            const CoexRun &r = runs[j];
+            if (r.done) continue;
+            CoexCase c{};
+            c.state = d_state + j * Q * n;
+            c.out = d_out + 4 * j;
+            c.G = r.G;
+            c.tau = r.current_tau();
+            c.rho0 = r.rho0;
+            c.hi = r.start_l;
+            c.lo = r.start_v;
+            c.mrt = r.mrt;
+            c.init = r.first ? 1 : 0;
+            table.push_back(c);
+            idx.push_back(j);
+        }
+        if (table.empty()) break;
+        e = hipMemcpy(d_cases, table.data(), sizeof(CoexCase) * table.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_coexistence_chunk(d_cases, int(table.size()), n, chunk, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(outs.data(), d_out, sizeof(double) * 4 * m, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (size_t j : idx) runs[j].take(&outs[4 * j]);
+    }
+    if (d_cases) (void)hipFree(d_cases);
+    if (d_out) (void)hipFree(d_out);
+    if (d_state) (void)hipFree(d_state);
+    return e;
+}
+
+int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, double rho0, double *rho_l,
+                     double *rho_v) {
+    if (!rho_l || !rho_v) return fail(LBM_ERR_INVALID_ARG, "output pointers are NULL");
+    if (mrt_in) {
+        const int mst = check_mrt(mrt_in);
+        if (mst != LBM_OK) return mst;
+    }
+    const int ast = check_coexistence_args(G, tau, psi, rho0);
+    if (ast != LBM_OK) return ast;
+    std::vector<CoexRun> runs{CoexRun(G, tau, rho0, mrt_params(mrt_in))};
+    const hipError_t e = run_coexistence(runs);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence: %s", hipGetErrorString(e));
+    if (runs[0].diverged) return fail(LBM_ERR_DIVERGED, "flat interface diverged for G=%g tau=%g", G, tau);
+    *rho_l = runs[0].bl;
+    *rho_v = runs[0].bv;
     return LBM_OK;
 }
 
@@ -639,6 +689,41 @@ int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, d
                         double *rho_v) {
     if (!mrt) return fail(LBM_ERR_INVALID_ARG, "mrt is NULL");
     return coexistence_impl(G, tau, mrt, psi, rho0, rho_l, rho_v);
+}
+
+int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
+                         double rho0, double *rho_l, double *rho_v, int32_t *status) {
+    if (m < 1) return fail(LBM_ERR_INVALID_ARG, "m must be >= 1");
+    if (!G || !tau || !rho_l || !rho_v || !status) return fail(LBM_ERR_INVALID_ARG, "an array pointer is NULL");
+    if (mrt) {
+        const int mst = check_mrt(mrt);
+        if (mst != LBM_OK) return mst;
+    }
+    const MrtParams mp = mrt_params(mrt);
+    std::vector<CoexRun> runs;
+    runs.reserve(size_t(m));
+    for (int32_t j = 0; j < m; ++j) {
+        const int ast = check_coexistence_args(G[j], tau[j], psi, rho0);
+        if (ast != LBM_OK) {
+            const std::string msg = g_err;
+            return fail(ast, "case %d: %s", j, msg.c_str());
+        }
+        runs.emplace_back(G[j], tau[j], rho0, mp);
+    }
+    const hipError_t e = run_coexistence(runs);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence_many: %s", hipGetErrorString(e));
+    int first_bad = -1, nbad = 0;
+    for (int32_t j = 0; j < m; ++j) {
+        const CoexRun &r = runs[size_t(j)];
+        status[j] = r.diverged ? LBM_ERR_DIVERGED : LBM_OK;
+        rho_l[j] = r.diverged ? NAN : r.bl;
+        rho_v[j] = r.diverged ? NAN : r.bv;
+        if (r.diverged && nbad++ == 0) first_bad = j;
+    }
+    if (nbad)
+        return fail(LBM_ERR_DIVERGED, "%d of %d flat interfaces diverged (first: case %d, G=%g tau=%g)", nbad, m,
+                    first_bad, G[first_bad], tau[first_bad]);
+    return LBM_OK;
 }
 
 int lbm_set_mrt(lbm_ctx *c, const lbm_mrt *mrt) {
@@ -1363,15 +1448,31 @@ int lbm_batch_init(lbm_batch *b, const lbm_ligament *specs) {
         a.noise_amp = g->noise_amp;
         a.seed = g->seed;
         if (!(a.rho_l > 0) || !(a.rho_v > 0)) {
-            st = lbm_coexistence(b->p[i].G, b->p[i].tau, b->p[i].psi, b->p[i].rho0, &a.rho_l, &a.rho_v);
-            if (st == LBM_ERR_DIVERGED) {
-                // The flat interface itself is unstable at this (G, tau): the case
-                // starts frozen, with non-finite densities its diagnostics report.
-                a.rho_l = a.rho_v = NAN;
-            } else if (st != LBM_OK) {
+            st = check_coexistence_args(b->p[i].G, b->p[i].tau, b->p[i].psi, b->p[i].rho0);
+            if (st != LBM_OK) {
                 const std::string m = g_err;
                 return fail(st, "case %d: %s", i, m.c_str());
             }
+        }
+    }
+    // Densities of the cases that need them: their flat-interface runs advance
+    // together, one workgroup each.  A run that diverges (the flat interface
+    // itself is unstable at that G and tau) leaves its case frozen from the
+    // start, with non-finite densities its diagnostics report.
+    std::vector<CoexRun> runs;
+    std::vector<int> need;
+    for (int i = 0; i < b->n; ++i)
+        if (!(args[i].rho_l > 0) || !(args[i].rho_v > 0)) {
+            runs.emplace_back(b->p[i].G, b->p[i].tau, b->p[i].rho0, MrtParams{});
+            need.push_back(i);
+        }
+    if (!runs.empty()) {
+        const hipError_t ce = run_coexistence(runs);
+        if (ce != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_batch_init: %s", hipGetErrorString(ce));
+        for (size_t k = 0; k < runs.size(); ++k) {
+            LigamentArgs &a = args[size_t(need[k])];
+            a.rho_l = runs[k].diverged ? NAN : runs[k].bl;
+            a.rho_v = runs[k].diverged ? NAN : runs[k].bv;
         }
     }
     hipError_t e = hipSuccess;

@@ -17,6 +17,15 @@ struct MrtParams {
     double s_e, s_eps, s_q, s_pi, s_m, s_j;
 };
 
+// One flat-interface run of a coexistence launch.
+struct CoexCase {
+    double *state;  // [19][n] populations, kept between chunks
+    double *out;    // rho(n/2), rho(0), largest density change over the chunk, non-finite flag
+    double G, tau, rho0, hi, lo;
+    MrtParams mrt;
+    int init;       // 1: start from the tanh profile between lo and hi
+};
+
 // Arguments of one fused step launch over one grid.
 struct StepArgs {
     const void *src;
@@ -126,13 +135,12 @@ hipError_t launch_droplets_label(const LatticeRef &L, double rho_mid, const Drop
 // Writes one entry per component (at most cap) into out, in no particular order.
 hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *out, int cap, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
-// Flat-interface coexistence run: `chunk` steps on the 1 x 1 x n slab held in
-// `state` ([19][n] doubles); init != 0 first writes the start profile
-// (liquid hi on [n/4, 3n/4), vapour lo elsewhere, tanh of width 4).
-// out[0] = rho(n/2), out[1] = rho(0), out[2] = max |rho - rho_before| over
-// the chunk, out[3] = 1 if a non-finite density appeared.
-hipError_t launch_coexistence_chunk(double *state, int n, double G, double tau, double rho0,
-                                    const MrtParams &mrt, double hi, double lo, int chunk, int init,
-                                    double *out, hipStream_t s);
+// Flat-interface coexistence runs, one workgroup each: `chunk` steps on the
+// 1 x 1 x n slab held in each case's `state` ([19][n] doubles); init != 0
+// first writes the start profile (liquid hi on [n/4, 3n/4), vapour lo
+// elsewhere, tanh of width 4).  out[0] = rho(n/2), out[1] = rho(0),
+// out[2] = max |rho - rho_before| over the chunk, out[3] = 1 if a non-finite
+// density appeared.  The table `cases` is in device memory.
+hipError_t launch_coexistence_chunk(const CoexCase *cases, int ncases, int n, int chunk, hipStream_t s);
 
 }  // namespace lbm

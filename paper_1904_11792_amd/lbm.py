@@ -106,6 +106,8 @@ _SIGS = {
     "lbm_coexistence": (ctypes.c_int, [_d, _d, _i32, _d, _P(_d), _P(_d)]),
     "lbm_equal_area": (ctypes.c_int, [_d, _i32, _d, _P(_d), _P(_d)]),
     "lbm_coexistence_mrt": (ctypes.c_int, [_d, _d, _P(lbm_mrt), _i32, _d, _P(_d), _P(_d)]),
+    "lbm_coexistence_many": (ctypes.c_int, [_i32, _P(_d), _P(_d), _P(lbm_mrt), _i32, _d, _P(_d), _P(_d),
+                                            _P(_i32)]),
     "lbm_set_mrt": (ctypes.c_int, [_vp, _P(lbm_mrt)]),
     "lbm_init_ligament": (ctypes.c_int, [_vp, _P(lbm_ligament)]),
     "lbm_step": (ctypes.c_int, [_vp, _i64]),
@@ -190,6 +192,25 @@ def lbm_coexistence(G: float, tau: float, psi: int = LBM_PSI_EXP, rho0: float = 
         _check(_lib.lbm_coexistence_mrt(G, tau, ctypes.byref(m), psi, rho0, ctypes.byref(rl),
                                         ctypes.byref(rv)))
     return rl.value, rv.value
+
+
+def lbm_coexistence_many(G, tau, psi: int = LBM_PSI_EXP, rho0: float = 1.0, mrt: dict | None = None):
+    """lbm_coexistence for each (G[j], tau[j]), all runs advanced together.
+
+    Returns (rho_l, rho_v, status) as numpy arrays; a diverged run has status
+    LBM_ERR_DIVERGED and NaN densities (no exception for that)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    if G.shape != tau.shape or G.ndim != 1:
+        raise ValueError("G and tau must be 1-D arrays of one length")
+    m = G.size
+    rl, rv = np.empty(m), np.empty(m)
+    st = np.empty(m, dtype=np.int32)
+    dp = lambda a: a.ctypes.data_as(_P(_d))
+    mp = ctypes.byref(make_mrt(**mrt)) if mrt is not None else None
+    _check(_lib.lbm_coexistence_many(m, dp(G), dp(tau), mp, psi, rho0, dp(rl), dp(rv),
+                                     st.ctypes.data_as(_P(_i32))), ok=(LBM_OK, LBM_ERR_DIVERGED))
+    return rl, rv, st
 
 
 def lbm_set_mrt(ctx, mrt: dict | None) -> None:

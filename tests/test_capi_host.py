@@ -91,6 +91,30 @@ def test_coexistence_rejects_subcritical_and_bad_tau(lbm):
     assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
 
 
+def test_coexistence_many_validates_every_case_before_device_work(lbm):
+    import ctypes
+
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_coexistence_many([-5.5, -3.0, -5.5], [0.8, 0.8, 0.8])
+    assert e.value.status == lbm.LBM_ERR_INVALID_ARG and "case 1" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_coexistence_many([-5.5, -5.5], [0.8, 0.5])
+    assert "case 1" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_coexistence_many([-5.5], [0.8], psi=3)
+    assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_coexistence_many([-5.5], [0.8], mrt={"s_e": 2.5})
+    with pytest.raises(ValueError):
+        lbm.lbm_coexistence_many([-5.5, -5.5], [0.8])
+    d = ctypes.c_double(0.0)
+    i = ctypes.c_int32(0)
+    assert lbm._lib.lbm_coexistence_many(0, ctypes.byref(d), ctypes.byref(d), None, 0, 1.0, ctypes.byref(d),
+                                         ctypes.byref(d), ctypes.byref(i)) == lbm.LBM_ERR_INVALID_ARG
+    assert lbm._lib.lbm_coexistence_many(1, ctypes.byref(d), None, None, 0, 1.0, ctypes.byref(d),
+                                         ctypes.byref(d), ctypes.byref(i)) == lbm.LBM_ERR_INVALID_ARG
+
+
 def test_mrt_rates_are_validated_before_device_work(lbm):
     for bad in ({"s_e": 0.0}, {"s_q": 2.0}, {"s_m": float("nan")}, {"s_j": 2.5}):
         with pytest.raises(lbm.LbmError) as e:

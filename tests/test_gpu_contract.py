@@ -87,6 +87,38 @@ def test_divergence_reported_not_raised(lbm):
     assert d["diverged"] and d["nonfinite"] == 1
 
 
+def test_coexistence_many_matches_single_runs(lbm):
+    """The runs of lbm_coexistence_many advance together but each follows its
+    own stages and stopping rule: every converged run must give bit for bit
+    the densities of lbm_coexistence, a run whose flat interface diverges
+    (tau near 1/2, strong attraction) must report it without spoiling the
+    others, and shared MRT rates must give the MRT single runs."""
+    import math
+    import time
+
+    G = [-5.5, -5.5, -5.3, -7.5, -6.0]
+    tau = [1.0, 0.8, 0.6241, 0.5001, 1.2]
+    t0 = time.perf_counter()
+    rl, rv, st = lbm.lbm_coexistence_many(G, tau)
+    t_many = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for j in range(len(G)):
+        if j == 3:
+            assert st[j] == lbm.LBM_ERR_DIVERGED and math.isnan(rl[j]) and math.isnan(rv[j])
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.lbm_coexistence(G[j], tau[j])
+            assert e.value.status == lbm.LBM_ERR_DIVERGED
+        else:
+            assert st[j] == lbm.LBM_OK
+            assert (rl[j], rv[j]) == lbm.lbm_coexistence(G[j], tau[j])
+    print(f"{len(G)} runs together {t_many:.2f} s, one by one {time.perf_counter() - t0:.2f} s")
+    mrt = dict(lbm.MRT_DEFAULT)
+    rl, rv, st = lbm.lbm_coexistence_many([-5.5, -5.5], [0.75, 1.3], mrt=mrt)
+    assert list(st) == [lbm.LBM_OK, lbm.LBM_OK]
+    for j, t in enumerate((0.75, 1.3)):
+        assert (rl[j], rv[j]) == lbm.lbm_coexistence(-5.5, t, mrt=mrt)
+
+
 def test_batch_freezes_diverged_case(lbm):
     import torch
 
