@@ -296,16 +296,20 @@ int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
  * Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
  * nodes (one thread each) marching zchunk planes along z.  Supported tiles:
  * see lbm_list_tiles.  tile_x = 0 selects a tile shaped at run time for the
- * grid, for a workgroup of tile_y threads (512 or 1024): width min(nx, 128)
- * for 512 threads or min(nx, 256) for 1024 (whole rows up to that width),
- * height balanced over ny with at most tile_y nodes and 64 rows.
- * zchunk >= 1.  The FP64 kernel is slow with 1024 threads (its registers do
- * not fit), the other storages run fastest there on grids of nx >= 128.
- * A new context starts on the shape cached by lbm_autotune for its grid, else
- * on the default: the run-time tile of 1024 threads (512 for FP64 or
- * nx < 128) and the z chunk that gives about 256 workgroups (at least 4
- * planes on grids of 2^22 nodes or more, where the two extra psi planes of a
- * chunk cost HBM traffic; smaller grids live in the caches).
+ * grid, for a workgroup of tile_y threads (512 or 1024): nx split evenly
+ * into the fewest tiles at most 128 (512 threads) or 256 (1024) wide, the
+ * width rounded up to a multiple of 32 when nx is one (whole rows when nx
+ * fits one tile); height balanced over ny with at most tile_y nodes and 64
+ * rows.  zchunk >= 1.  The FP64 kernel is slow with 1024 threads (its
+ * registers do not fit), the other storages run fastest there on grids of
+ * nx >= 128.  A new context starts on the shape cached by lbm_autotune for
+ * its grid, else on the default: the run-time tile of 1024 threads (512 for
+ * FP64 or nx < 128) and the z chunk that minimises rounds x (chunk + 18),
+ * where a round is as many workgroups as the device holds at once (256 for
+ * one 1024-thread workgroup per compute unit) and 18 planes charge a round's
+ * start-up and tail; at least 4 planes on grids of 2^22 nodes or more, where
+ * the two extra psi planes of a chunk cost HBM traffic (smaller grids live
+ * in the caches).
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

@@ -109,6 +109,9 @@ int find_tile(int tx, int ty);
 // (tile_has_mrt).
 hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s);
 bool tile_has_mrt(int tile_index);
+// Workgroups of this tile's step kernel that the device runs at once (compute
+// units x resident workgroups per unit); 0 if the runtime cannot say.
+int launch_slots(int tile_index, int storage);
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
                              const int4 *items, int nitems, const int32_t *frozen, int parity,
                              hipStream_t s);

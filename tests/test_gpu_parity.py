@@ -243,11 +243,14 @@ def test_shifted_storage_round_trip_is_exact(lbm, storage):
     assert torch.equal(back, pop)
 
 
+@pytest.mark.parametrize("nx", [301, 480])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_run_time_tiles_on_wide_grid(lbm, oracle_mod, storage):
-    """Both run-time shaped tiles on a grid wider than either width cap (a
-    ragged last column of tiles) and a z chunk that leaves a ragged tail."""
-    nx, ny, nz = 300, 9, 11
+def test_run_time_tiles_on_wide_grid(lbm, oracle_mod, storage, nx):
+    """Both run-time shaped tiles on grids wider than either width cap, with a
+    ragged last column of tiles (301: balanced widths 101 + 101 + 99 and
+    151 + 150; 480, a multiple of 32: widths rounded to 32, 128 x 3 + 96 and
+    256 + 224), and a z chunk that leaves a ragged tail."""
+    ny, nz = 9, 11
     spec = dict(R0=3.0, amp_rel=0.1, wavelength=11.0, noise_amp=1e-3, seed=12)
     f0 = oracle_mod.init_ligament(nx, ny, nz, rho_l=RHO_L, rho_v=RHO_V, axis=0, **spec)
     ref = oracle_mod.run(f0, 4, 0.9, -5.5)
