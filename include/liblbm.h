@@ -304,12 +304,13 @@ int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
  * registers do not fit), the other storages run fastest there on grids of
  * nx >= 128.  A new context starts on the shape cached by lbm_autotune for
  * its grid, else on the default: the run-time tile of 1024 threads (512 for
- * FP64 or nx < 128) and the z chunk that minimises rounds x (chunk + 18),
- * where a round is as many workgroups as the device holds at once (256 for
- * one 1024-thread workgroup per compute unit) and 18 planes charge a round's
- * start-up and tail; at least 4 planes on grids of 2^22 nodes or more, where
- * the two extra psi planes of a chunk cost HBM traffic (smaller grids live
- * in the caches).
+ * FP64 or nx < 128) and, on grids of 2^22 nodes or more, the z chunk of at
+ * least 4 planes that minimises rounds x (chunk + 18), where a round is as
+ * many workgroups as the device holds at once (256 for one 1024-thread
+ * workgroup per compute unit) and 18 planes charge a round's start-up, the
+ * two extra psi planes of each chunk and the tail; smaller grids, which live
+ * in the caches, take the chunk that gives about 256 workgroups (down to one
+ * plane).
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

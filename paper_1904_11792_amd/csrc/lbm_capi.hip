@@ -195,26 +195,33 @@ lbm_launch default_launch(const lbm_params *p) {
     int tw, th;
     tile_dims(l, p->nx, p->ny, &tw, &th);
     const int64_t tiles = int64_t((p->nx + tw - 1) / tw) * ((p->ny + th - 1) / th);
-    // A z chunk re-gathers two extra planes for psi.  On grids that live in
-    // HBM keep chunks of at least 4 planes; small grids live in the caches,
-    // where more workgroups pay more than the extra gathers cost (32x32x64 on
-    // MI355X: 1.7x (FP32) and 1.9x (FP64) faster at chunks of 1 than of 4).
+    // A z chunk re-gathers two extra planes for psi.  Small grids (under 2^22
+    // nodes) live in the caches, where more workgroups pay more than the extra
+    // gathers cost: about 256 workgroups with chunks down to one plane
+    // (32x32x64 on MI355X: 1.7x (FP32) and 1.9x (FP64) faster at chunks of 1
+    // than of 4).
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    const int64_t zmin = n >= (int64_t(1) << 22) ? 4 : 1;
-    // The launch runs in rounds of `slots` workgroups (those resident at
-    // once).  Cost model: rounds x (z chunk + kRoundPlanes), where
-    // kRoundPlanes charges each round's start-up, boundary re-gathers and
-    // tail in plane times (about 18, measured on MI355X: 256x256x1024 FP32
-    // with 512 workgroups of 128 planes takes 1.067x the time of 256 of 256).
-    // A count of workgroups just above a multiple of the slots costs a whole
-    // extra round, which the model avoids.
-    constexpr int64_t kRoundPlanes = 18;
+    if (n < (int64_t(1) << 22)) {
+        const int64_t chunks = (256 + tiles - 1) / tiles;
+        const int64_t zc = (p->nz + chunks - 1) / chunks;
+        l.zchunk = int(zc < 1 ? 1 : zc);
+        return l;
+    }
+    // Grids in HBM: chunks of at least 4 planes, and a launch that runs in
+    // rounds of `slots` workgroups (those resident at once).  Cost model:
+    // rounds x (z chunk + kRoundPlanes), where kRoundPlanes charges each
+    // round's start-up, boundary re-gathers and tail in plane times (about 18,
+    // measured on MI355X: 256x256x1024 FP32 with 512 workgroups of 128 planes
+    // takes 1.067x the time of 256 of 256).  A count of workgroups just above
+    // a multiple of the slots costs a whole extra round, which the model
+    // avoids.
+    constexpr int64_t kRoundPlanes = 18, kMinChunk = 4;
     int64_t slots = launch_slots(find_tile(l.tile_x, l.tile_y), p->storage);
     if (slots <= 0) slots = 256;
     int64_t best_zc = p->nz, best_cost = INT64_MAX;
     for (int64_t k = 1; k <= p->nz && k <= 65536; ++k) {
         const int64_t zc = (p->nz + k - 1) / k;
-        if (zc < zmin) break;
+        if (zc < kMinChunk) break;
         if (k > 1 && zc == (p->nz + k - 2) / (k - 1)) continue;  // same chunk as k - 1
         const int64_t wgs = tiles * ((p->nz + zc - 1) / zc);
         const int64_t cost = (wgs + slots - 1) / slots * (zc + kRoundPlanes);
@@ -223,7 +230,6 @@ lbm_launch default_launch(const lbm_params *p) {
             best_zc = zc;
         }
     }
-    if (best_zc < zmin) best_zc = zmin;
     if (best_zc > p->nz) best_zc = p->nz;
     l.zchunk = int(best_zc);
     return l;
