@@ -322,8 +322,9 @@ int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *l);
 int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count);
 
 /*
- * Autotuner: time each supported tile shape and z-chunk on this context's
- * grid (steps_per_candidate launches from the current lattice into the
+ * Autotuner: time the context's launch, the default launch and each
+ * supported tile shape with z chunks of 1, 2, 4, ..., 256 planes on this
+ * context's grid (steps_per_candidate launches from the current lattice into the
  * spare one, so the state is unchanged), pick the fastest, set it, and store
  * it in the JSON cache named by the environment variable LBM_TUNE_CACHE (if
  * set) keyed by device architecture, storage and grid.  A later lbm_create

@@ -1032,33 +1032,40 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, doub
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
+    // Candidates: the context's launch, the default launch, then every
+    // compiled tile with z chunks of 1 to 256 planes.
+    std::vector<lbm_launch> cands{c->launch, default_launch(&c->p)};
     const int zcs[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
-    double best_t = INFINITY;
-    lbm_launch bl = c->launch;
-    const double nodes = double(c->p.nx) * c->p.ny * c->p.nz;
-    for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
+    for (int ti = 0; ti < num_tiles(); ++ti) {
         lbm_launch l;
         tile_shape(ti, &l.tile_x, &l.tile_y);
         if (l.tile_x > 2 * c->p.nx && l.tile_x > 32) continue;  // mostly idle lanes
-        if (c->mrt.on && !tile_has_mrt(ti)) continue;
         for (int zc : zcs) {
             if (zc > c->p.nz && zc != zcs[0]) break;
             l.zchunk = zc;
-            const StepArgs A = step_args(c, l, c->cur);  // cur -> spare: state untouched
-            e = launch_step(ti, c->p.storage, A, c->stream);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
-                e = launch_step(ti, c->p.storage, A, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
-            const double t = ms / steps_per_candidate;
-            if (t < best_t) {
-                best_t = t;
-                bl = l;
-            }
+            cands.push_back(l);
+        }
+    }
+    double best_t = INFINITY;
+    lbm_launch bl = c->launch;
+    const double nodes = double(c->p.nx) * c->p.ny * c->p.nz;
+    for (const lbm_launch &l : cands) {
+        const int ti = find_tile(l.tile_x, l.tile_y);
+        if (ti < 0 || (c->mrt.on && !tile_has_mrt(ti))) continue;
+        const StepArgs A = step_args(c, l, c->cur);  // cur -> spare: state untouched
+        e = launch_step(ti, c->p.storage, A, c->stream);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
+            e = launch_step(ti, c->p.storage, A, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        const double t = ms / steps_per_candidate;
+        if (t < best_t) {
+            best_t = t;
+            bl = l;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
