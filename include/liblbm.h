@@ -320,6 +320,14 @@ int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *l);
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *l);
 /* Copy up to max supported tiles into out; *count receives the total. */
 int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count);
+/*
+ * The default launch for these parameters (as lbm_create would choose it
+ * without a cached shape) and, if tile_w / tile_h are not NULL, the run-time
+ * tile's width and height on this grid.  The round size comes from the
+ * current device; without one it is taken as 256 workgroups.  Errors:
+ * INVALID_ARG (params as for lbm_workspace_bytes, out NULL).
+ */
+int lbm_default_launch(const lbm_params *p, lbm_launch *out, int32_t *tile_w, int32_t *tile_h);
 
 /*
  * Autotuner: time the context's launch, the default launch and each

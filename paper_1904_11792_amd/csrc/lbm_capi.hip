@@ -1024,6 +1024,18 @@ int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count) {
     return LBM_OK;
 }
 
+int lbm_default_launch(const lbm_params *p, lbm_launch *out, int32_t *tile_w, int32_t *tile_h) {
+    const int st = validate_params(p);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    *out = default_launch(p);
+    int tw = 0, th = 0;
+    tile_dims(*out, p->nx, p->ny, &tw, &th);
+    if (tile_w) *tile_w = tw;
+    if (tile_h) *tile_h = th;
+    return LBM_OK;
+}
+
 int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, double *best_mlups) {
     int st = check_ctx(c);
     if (st != LBM_OK) return st;

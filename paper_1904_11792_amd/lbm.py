@@ -122,6 +122,7 @@ _SIGS = {
     "lbm_set_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_get_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_list_tiles": (ctypes.c_int, [_P(lbm_launch), _i32, _P(_i32)]),
+    "lbm_default_launch": (ctypes.c_int, [_P(lbm_params), _P(lbm_launch), _P(_i32), _P(_i32)]),
     "lbm_autotune": (ctypes.c_int, [_vp, _i32, _P(lbm_launch), _P(_d)]),
     "lbm_set_graph_chunk": (ctypes.c_int, [_vp, _i32]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -292,6 +293,13 @@ def lbm_list_tiles() -> list[tuple[int, int]]:
     cnt = _i32()
     _check(_lib.lbm_list_tiles(buf, 64, ctypes.byref(cnt)))
     return [(buf[i].tile_x, buf[i].tile_y) for i in range(min(cnt.value, 64))]
+
+
+def lbm_default_launch(params: lbm_params):
+    """((tile_x, tile_y, zchunk), (tile_w, tile_h)): the default launch and its run-time tile."""
+    l, tw, th = lbm_launch(), _i32(), _i32()
+    _check(_lib.lbm_default_launch(ctypes.byref(params), ctypes.byref(l), ctypes.byref(tw), ctypes.byref(th)))
+    return (l.tile_x, l.tile_y, l.zchunk), (tw.value, th.value)
 
 
 def lbm_autotune(ctx, steps_per_candidate: int = 5):

@@ -91,6 +91,31 @@ def test_coexistence_rejects_subcritical_and_bad_tau(lbm):
     assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
 
 
+def test_default_launch_rules(lbm):
+    """The default launch's documented rules, evaluated on the host (no device
+    here, so a round is 256 workgroups)."""
+    P = lambda nx, ny, nz, st="f32": lbm.make_params(nx, ny, nz, 0.8, -5.5, storage=st)
+    # whole 256-wide rows, 64 tiles x 4 chunks = one round of 256 workgroups
+    assert lbm.lbm_default_launch(P(256, 256, 1024)) == ((0, 1024, 256), (256, 4))
+    # 280 = 140 + 140 (not 256 + 24); 40 bands x 2 = 80 tiles, 3 chunks of 210 = 240 workgroups
+    assert lbm.lbm_default_launch(P(280, 280, 628)) == ((0, 1024, 210), (140, 7))
+    # 480 is a multiple of 32: widths rounded up to 256 (256 + 224)
+    assert lbm.lbm_default_launch(P(480, 480, 256))[1] == (256, 4)
+    assert lbm.lbm_default_launch(P(301, 9, 11))[1] == (151, 5)
+    # more tiles than a round: one chunk, the whole z extent
+    assert lbm.lbm_default_launch(P(1024, 1024, 1024)) == ((0, 1024, 1024), (256, 4))
+    # FP64 and narrow grids take 512 threads; FP64 128 x 4 tiles, 2 chunks of 512
+    assert lbm.lbm_default_launch(P(256, 256, 1024, "f64")) == ((0, 512, 512), (128, 4))
+    assert lbm.lbm_default_launch(P(112, 112, 1000))[0][:2] == (0, 512)
+    # cache-resident grids (< 2^22 nodes): about 256 workgroups, chunks down to one plane
+    assert lbm.lbm_default_launch(P(32, 32, 64, "f64")) == ((0, 512, 1), (32, 16))
+    assert lbm.lbm_default_launch(P(64, 64, 144)) == ((0, 512, 5), (64, 8))
+    # HBM grids keep chunks of at least 4 planes
+    assert lbm.lbm_default_launch(P(2048, 2048, 64))[0][2] >= 4
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_default_launch(P(0, 4, 4))
+
+
 def test_coexistence_many_validates_every_case_before_device_work(lbm):
     import ctypes
 
