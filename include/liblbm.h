@@ -398,6 +398,8 @@ int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out);
 /* Per-case FP64 export, as lbm_get_fields, for case `index`. */
 int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho, double *u,
                          double *force, double *pop, int32_t on_device);
+/* Launch of the batched step (z chunk >= 4); the default is the 512-thread
+ * run-time tile, shaped per case, with z chunks of 8 planes. */
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
 /*
  * Autotuner of the batched launch: time each tile shape and z chunk (>= 4)

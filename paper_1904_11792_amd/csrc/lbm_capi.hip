@@ -1394,7 +1394,9 @@ lbm_launch batch_default_launch(int n, const lbm_params *p) {
     lbm_launch l;
     l.tile_x = 0;  // each case gets its own full-row tile shape
     l.tile_y = 512;
-    l.zchunk = 16;
+    // Measured on MI355X over the 51 live cases of the 64-ligament batch:
+    // z chunks of 5-8 planes within 1% of each other, 16 planes 4% slower.
+    l.zchunk = 8;
     return l;
 }
 
