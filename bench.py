@@ -17,6 +17,7 @@ bounded sample of the same workload.
 
 Studies (one JSON line each, not the benchmark line):
   --form precision    FP16/BF16 shifted storage against FP32/FP64
+  --form shift        FP16 storage error against the shift density rho_ref
   --form convergence  t_b / t_cap against 1/R, FP32 and FP64
   --form paper        the paper's Table 1 sweep (G = -5.3, Oh = 0.1)
   --form small        the small FP64 ligament and R = 8, 16 of the convergence
@@ -130,7 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
     ap.add_argument("--form", default="single",
-                    choices=["single", "batch", "precision", "convergence", "paper", "small"])
+                    choices=["single", "batch", "precision", "shift", "convergence", "paper", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
                     help="mrt: the multiple-relaxation-time collision with the suggested rates "
@@ -175,6 +176,8 @@ def main():
         return bench_batch(args, lbm, workloads, stream)
     if args.form == "precision":
         return study_precision(args, lbm, workloads, stream)
+    if args.form == "shift":
+        return study_shift(args, lbm, workloads, stream)
     if args.form == "convergence":
         return study_convergence(args, lbm, workloads, stream)
     if args.form == "paper":
@@ -290,15 +293,16 @@ def sweep(lat, spec, stream, storage):
 
 
 def _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, max_steps, every, extra_after=0,
-                  mrt=None):
+                  mrt=None, rho_ref=None):
     """Step one ligament to break-up (neck sampled every `every` steps), then
-    `extra_after` more steps; returns t_b, time per step, droplets, mass drift."""
+    `extra_after` more steps; returns t_b, time per step, droplets, mass drift.
+    Shifted storage uses rho_ref (default: the vapour density)."""
     import torch
 
     from paper_1904_11792_amd import analysis
 
-    lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage, rho_ref=rho_v,
-                      stream=stream, mrt=mrt)
+    lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage=storage,
+                      rho_ref=rho_v if rho_ref is None else rho_ref, stream=stream, mrt=mrt)
     lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength, rho_l=rho_l,
                       rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
     m0 = lat.diagnostics()["mass"]
@@ -362,6 +366,37 @@ def study_precision(args, lbm, workloads, stream):
         out.append({"case": spec.name, "G": spec.G, "tau": spec.tau, "rho_l": rho_l, "rho_v": rho_v,
                     "results": res})
     print(json.dumps({"study": "precision", "grid": [base.nx, base.ny, base.nz], "cases": out}))
+
+
+def study_shift(args, lbm, workloads, stream):
+    """Shifted FP16 storage: break-up time and mass drift against the FP64 run
+    for several shift densities rho_ref (vapour, 0, the mean of the two phases,
+    1) on the large ligament (two noise seeds, G -6.0, tau 1.0) and the R = 32
+    grid of the convergence series."""
+    import dataclasses
+
+    base = workloads.LARGE_FP32
+    cases = [base, dataclasses.replace(base, name=base.name + " seed 2", seed=2),
+             dataclasses.replace(base, name=base.name + " G=-6.0", G=-6.0),
+             dataclasses.replace(base, name=base.name + " tau=1.0", tau=1.0), workloads.convergence(32)]
+    out = []
+    for spec in cases:
+        rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
+        runs = [("f64", None, "-")] + [("f16s", r, name) for name, r in
+                                      (("rho_v", rho_v), ("0", 0.0), ("mid", 0.5 * (rho_l + rho_v)), ("1", 1.0))]
+        ref, rows = None, []
+        for storage, rref, name in runs:
+            print(f"# {spec.name} {storage} rho_ref={name}", file=sys.stderr, flush=True)
+            r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, 30000, every=10, rho_ref=rref)
+            if storage == "f64":
+                ref = r["t_b"]
+            err = None if (ref is None or r["t_b"] is None) else (r["t_b"] - ref) / ref
+            rows.append({"storage": storage, "rho_ref": name, "t_b": r["t_b"], "t_b_rel_err_vs_f64": err,
+                         "mass_drift": r["mass_drift"], "droplets": r["droplets"]})
+            print(f"# {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+        out.append({"case": spec.name, "G": spec.G, "tau": spec.tau, "rho_l": rho_l, "rho_v": rho_v,
+                    "rows": rows})
+    print(json.dumps({"study": "fp16_shift_density", "cases": out}))
 
 
 def study_convergence(args, lbm, workloads, stream):
