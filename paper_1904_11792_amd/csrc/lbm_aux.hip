@@ -30,7 +30,7 @@ __device__ inline int64_t node_index(int x, int y, int z, int nx, int ny) {
 // under pull streaming: site x - c_a.
 __device__ inline int64_t pull_source(int a, int x, int y, int z, const LatticeRef &L) {
     return a * L.pop_stride + int64_t(wrapi(z - kCZ[a], L.nz)) * L.plane_stride +
-           int64_t(wrapi(y - kCY[a], L.ny)) * L.row_stride + wrapi(x - kCX[a], L.nx);
+           row_offset(wrapi(y - kCY[a], L.ny), L.row_stride, L.rec_shift, L.nx) + wrapi(x - kCX[a], L.nx);
 }
 
 template <int ST>

@@ -52,7 +52,7 @@ int validate_params(const lbm_params *p) {
         return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     // Offsets within a z plane (19 nx ny populations) and node indices are 32-bit.
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    if (int64_t(Q) * p->nx * p->ny > int64_t(0x7fffffff))
+    if (int64_t(Q) * p->nx * (int64_t(p->ny) + 7) > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane holds more than 2^31 - 1 populations", p->nx, p->ny);
     if (n > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1 nodes", (long long)n);
@@ -70,21 +70,42 @@ int validate_params(const lbm_params *p) {
 
 struct Layout {
     int64_t S;       // population stride (elements)
-    int R, P;        // row and plane strides (elements)
+    int R, P;        // record and plane strides (elements)
+    int rec_shift;   // rows per record = 2^rec_shift
     size_t lat_bytes, off_lat1, off_part, off_slices, off_latest, off_ring, total;
     int nparts, nslices;
 };
 
+// Rows per record: the smallest power of two k <= 8 (and <= ny) whose
+// population segment, k nx elements, holds at least 2 KiB.  Measured on
+// MI355X against one row per record (default launches, FP32): 24-wide grids
+// 21% faster, 48-wide 10%, 80-wide 7%, 112-wide 6%, the 64-ligament batch 9%;
+// 256-wide unchanged within 0.4%.
+int record_shift(int nx, int ny, int storage) {
+    constexpr size_t kRecordBytes = 2048;
+    int s = 0;
+    while (s < 3 && size_t(nx) * elem_bytes(storage) * (size_t(1) << s) < kRecordBytes && (2 << s) <= ny) ++s;
+    return s;
+}
+
+// Rows padded to whole records.
+int64_t padded_rows(int ny, int rec_shift) {
+    const int64_t k = int64_t(1) << rec_shift;
+    return (ny + k - 1) / k * k;
+}
+
 Layout layout_of(const lbm_params *p) {
     Layout L;
-    const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    // Row-interleaved [z][y][a][x]: the 19 population segments of one grid
-    // row are contiguous (population stride nx, row stride 19 nx, plane
-    // stride 19 nx ny).
-    L.S = p->nx;
-    L.R = Q * p->nx;
-    L.P = Q * p->nx * p->ny;
-    const int64_t cells = int64_t(Q) * n;
+    // Records of k rows, [z][y / k][a][y % k][x]: the 19 population segments
+    // of k grid rows are contiguous (population stride k nx, record stride
+    // 19 k nx, plane stride 19 nx ny' with ny' = ny rounded up to records).
+    L.rec_shift = record_shift(p->nx, p->ny, p->storage);
+    const int k = 1 << L.rec_shift;
+    const int64_t nyp = padded_rows(p->ny, L.rec_shift);
+    L.S = int64_t(k) * p->nx;
+    L.R = Q * k * p->nx;
+    L.P = int(int64_t(Q) * p->nx * nyp);
+    const int64_t cells = int64_t(Q) * p->nx * nyp * p->nz;
     L.lat_bytes = align_up(size_t(cells) * elem_bytes(p->storage), 256);
     L.off_lat1 = L.lat_bytes;
     L.nparts = diag_blocks(p->nx, p->ny, p->nz);
@@ -294,6 +315,7 @@ LatticeRef lattice_ref(const lbm_ctx *c, int which) {
     L.pop_stride = c->lay.S;
     L.row_stride = c->lay.R;
     L.plane_stride = c->lay.P;
+    L.rec_shift = c->lay.rec_shift;
     L.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
     L.frozen = nullptr;
     L.pair[0] = L.pair[1] = nullptr;
@@ -315,6 +337,7 @@ StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
     A.pop_stride = c->lay.S;
     A.row_stride = c->lay.R;
     A.plane_stride = c->lay.P;
+    A.rec_shift = c->lay.rec_shift;
     A.tau = c->p.tau;
     A.G = c->p.G;
     A.rho0 = c->p.rho0;
@@ -1261,6 +1284,7 @@ LatticeRef batch_ref(const lbm_batch *b, int i, int which) {
     L.pop_stride = b->lay[i].S;
     L.row_stride = b->lay[i].R;
     L.plane_stride = b->lay[i].P;
+    L.rec_shift = b->lay[i].rec_shift;
     L.rho_ref = is_shifted(b->p[i].storage) ? b->p[i].rho_ref : 0.0;
     L.frozen = b->d_frozen + i;
     L.pair[0] = case_lat(b, i, 0);
@@ -1288,6 +1312,7 @@ hipError_t batch_upload(lbm_batch *b) {
         A.pop_stride = b->lay[i].S;
         A.row_stride = b->lay[i].R;
         A.plane_stride = b->lay[i].P;
+        A.rec_shift = b->lay[i].rec_shift;
         A.tau = b->p[i].tau;
         A.G = b->p[i].G;
         A.rho0 = b->p[i].rho0;

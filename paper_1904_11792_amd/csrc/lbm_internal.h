@@ -27,6 +27,14 @@ struct CoexCase {
 };
 
 // Arguments of one fused step launch over one grid.
+// Rows are stored in records of 2^rec_shift rows: a record holds, population
+// after population, the segments of its rows ([z][y / k][a][y % k][x] with
+// k = 2^rec_shift; k = 1 is row-interleaved [z][y][a][x]).  row_stride is the
+// record stride 19 k nx, pop_stride k nx.  Offset of row y within a plane:
+__host__ __device__ inline int row_offset(int y, int row_stride, int rec_shift, int nx) {
+    return (y >> rec_shift) * row_stride + (y & ((1 << rec_shift) - 1)) * nx;
+}
+
 struct StepArgs {
     const void *src;
     void *dst;
@@ -34,10 +42,10 @@ struct StepArgs {
     int tiles_x, tiles_y, zchunk, nchunks;
     int tile_w, tile_h;  // tile shape (used by the run-time shaped kernel)
     // element offset of population a at node (x, y, z):
-    //   a * pop_stride + z * plane_stride + y * row_stride + x
-    // (the part within a plane, y * row_stride + x + a * pop_stride, fits in 32 bits)
+    //   a * pop_stride + z * plane_stride + row_offset(y) + x
+    // (the part within a plane fits in 32 bits); see row_offset
     int64_t pop_stride;
-    int row_stride, plane_stride;
+    int row_stride, plane_stride, rec_shift;
     double tau, G, rho0, rho_ref;
     MrtParams mrt;
 };
@@ -68,7 +76,7 @@ struct LatticeRef {
     int nx, ny, nz;
     int storage;
     int64_t pop_stride;
-    int row_stride, plane_stride;
+    int row_stride, plane_stride, rec_shift;
     double rho_ref;
     // Batched cases only: when *frozen != 0 the state lives in pair[*frozen - 1]
     // (the lattice current when the case was frozen) instead of lat.
