@@ -52,7 +52,7 @@ int validate_params(const lbm_params *p) {
         return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     // Offsets within a z plane (19 nx ny populations) and node indices are 32-bit.
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    if (int64_t(Q) * p->nx * (int64_t(p->ny) + 7) > int64_t(0x7fffffff))
+    if (int64_t(Q) * p->nx * (int64_t(p->ny) + 31) > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane holds more than 2^31 - 1 populations", p->nx, p->ny);
     if (n > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1 nodes", (long long)n);
@@ -76,15 +76,21 @@ struct Layout {
     int nparts, nslices;
 };
 
-// Rows per record: the smallest power of two k <= 8 (and <= ny) whose
-// population segment, k nx elements, holds at least 2 KiB.  Measured on
-// MI355X against one row per record (default launches, FP32): 24-wide grids
-// 21% faster, 48-wide 10%, 80-wide 7%, 112-wide 6%, the 64-ligament batch 9%;
-// 256-wide unchanged within 0.4%.
+// Rows per record: the smallest power of two k (and at most ny / 2) whose
+// population segment, k nx elements, holds at least the target: 32 KiB with
+// k <= 32 when nx is a power of two from 64 to 1024, 2 KiB with k <= 8
+// otherwise.  Measured on MI355X (default launches, HIP events, against the
+// 2 KiB rule): power-of-two widths 64-512 3-5.5% faster in FP32 and FP64
+// (256 x 256 x 1024 FP32 1.909 -> 1.808 ms; k = 64 and beyond slower again),
+// about 1% in FP16S; other widths (24-480) equal or up to 2.6% slower with
+// the larger records, and fastest with segments of about 2 KiB (rows of
+// 24-112 nodes 6-21% faster at k = 8 than at k = 1).
 int record_shift(int nx, int ny, int storage) {
-    constexpr size_t kRecordBytes = 2048;
+    const bool pow2 = nx >= 64 && nx <= 1024 && (nx & (nx - 1)) == 0;
+    const size_t target = pow2 ? 32768 : 2048;
+    const int smax = pow2 ? 5 : 3;
     int s = 0;
-    while (s < 3 && size_t(nx) * elem_bytes(storage) * (size_t(1) << s) < kRecordBytes && (2 << s) <= ny) ++s;
+    while (s < smax && size_t(nx) * elem_bytes(storage) * (size_t(1) << s) < target && (2 << s) <= ny) ++s;
     return s;
 }
 
