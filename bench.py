@@ -43,8 +43,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# The step kernel, and the host code that sets its lattice layout and default
+# launch: a change to any of them invalidates the stored traffic figures.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1904_11792_amd", "csrc", f)
-                  for f in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h")]
+                  for f in ("lbm_step.hip", "lbm_device.h", "lbm_internal.h", "lbm_capi.hip")]
 
 
 def kernel_digest() -> str:
