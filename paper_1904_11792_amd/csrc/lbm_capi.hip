@@ -78,15 +78,17 @@ struct Layout {
 
 // Rows per record: the smallest power of two k (and at most ny / 2) whose
 // population segment, k nx elements, holds at least the target: 32 KiB with
-// k <= 32 when nx is a power of two from 64 to 1024, 2 KiB with k <= 8
-// otherwise.  Measured on MI355X (default launches, HIP events, against the
+// k <= 32 when nx is a power of two from 64 to 1024 and the grid (2^22 nodes
+// or more) lives in HBM, 2 KiB with k <= 8 otherwise (on cache-resident grids
+// the long records measured up to 6% slower, 64 x 64 x 144 FP64).  Measured on MI355X (default launches, HIP events, against the
 // 2 KiB rule): power-of-two widths 64-512 3-5.5% faster in FP32 and FP64
 // (256 x 256 x 1024 FP32 1.909 -> 1.808 ms; k = 64 and beyond slower again),
 // about 1% in FP16S; other widths (24-480) equal or up to 2.6% slower with
 // the larger records, and fastest with segments of about 2 KiB (rows of
 // 24-112 nodes 6-21% faster at k = 8 than at k = 1).
-int record_shift(int nx, int ny, int storage) {
-    const bool pow2 = nx >= 64 && nx <= 1024 && (nx & (nx - 1)) == 0;
+int record_shift(int nx, int ny, int nz, int storage) {
+    const bool in_hbm = int64_t(nx) * ny * nz >= (int64_t(1) << 22);
+    const bool pow2 = in_hbm && nx >= 64 && nx <= 1024 && (nx & (nx - 1)) == 0;
     const size_t target = pow2 ? 32768 : 2048;
     const int smax = pow2 ? 5 : 3;
     int s = 0;
@@ -105,7 +107,7 @@ Layout layout_of(const lbm_params *p) {
     // Records of k rows, [z][y / k][a][y % k][x]: the 19 population segments
     // of k grid rows are contiguous (population stride k nx, record stride
     // 19 k nx, plane stride 19 nx ny' with ny' = ny rounded up to records).
-    L.rec_shift = record_shift(p->nx, p->ny, p->storage);
+    L.rec_shift = record_shift(p->nx, p->ny, p->nz, p->storage);
     const int k = 1 << L.rec_shift;
     const int64_t nyp = padded_rows(p->ny, L.rec_shift);
     L.S = int64_t(k) * p->nx;
