@@ -103,7 +103,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, storage: str) -> dict:
             "write_scale": round(wscale, 4), "fetch_kib_raw": fs, "write_kib_raw": ws}
 
 
-def cpu_baseline(spec, rho_l, rho_v, budget_s=12.0):
+def cpu_baseline(spec, rho_l, rho_v, budget_s=18.0):
     """The FP64 oracle on a z-slab of the same ligament (bounded sample)."""
     import oracle
 
@@ -111,10 +111,10 @@ def cpu_baseline(spec, rho_l, rho_v, budget_s=12.0):
     f = oracle.init_ligament(spec.nx, spec.ny, nz_s, R0=spec.R0, amp_rel=spec.amp_rel,
                              wavelength=spec.wavelength, rho_l=rho_l, rho_v=rho_v,
                              noise_amp=spec.noise_amp, seed=spec.seed)
-    f = oracle.run(f, 1, spec.tau, spec.G)  # pages the arrays in
+    f = oracle.run(f, 2, spec.tau, spec.G)  # pages the arrays in, starts the threads
     t0 = time.perf_counter()
-    f = oracle.run(f, 2, spec.tau, spec.G)  # calibration
-    t1 = (time.perf_counter() - t0) / 2
+    f = oracle.run(f, 3, spec.tau, spec.G)  # calibration
+    t1 = (time.perf_counter() - t0) / 3
     steps = max(2, min(400, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     f = oracle.run(f, steps, spec.tau, spec.G)
