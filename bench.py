@@ -139,7 +139,8 @@ def main():
                     help="mrt: the multiple-relaxation-time collision with the suggested rates "
                          "of d'Humieres et al. and s_j = 1/tau")
     ap.add_argument("--graph-chunk", type=int, default=0)
-    ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice)")
+    ap.add_argument("--launch", default="", help="tile_x,tile_y,zchunk (default: library's choice; "
+                                                 "for --form batch the autotuner's)")
     ap.add_argument("--slab", type=int, default=0,
                     help="run the large ligament's first SLAB z planes only (one GPU's share of a "
                          "z-slab decomposition; periodic in z, no halo exchange)")
@@ -594,8 +595,12 @@ def bench_batch(args, lbm, workloads, stream):
     diags = b.diagnostics()
     live = [i for i, d in enumerate(diags) if d["nonfinite"] == 0]
     nodes = sum(cases[i].n for i in live)
-    launch, tuned = b.autotune(10)
-    print(f"# {len(live)} live cases, {nodes} nodes; autotuned launch {launch}", file=sys.stderr,
+    if args.launch:  # a fixed launch (profiling runs), else the autotuner's pick
+        launch = tuple(int(v) for v in args.launch.split(","))
+        b.set_launch(*launch)
+    else:
+        launch, tuned = b.autotune(20)
+    print(f"# {len(live)} live cases, {nodes} nodes; launch {launch}", file=sys.stderr,
           flush=True)
     chunk = args.graph_chunk or 100
     b.set_graph_chunk(chunk)

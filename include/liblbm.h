@@ -402,8 +402,8 @@ int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho
  * run-time tile, shaped per case, with z chunks of 8 planes. */
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
 /*
- * Autotuner of the batched launch: time each tile shape and z chunk (>= 4)
- * over the whole item list (launches from the current lattices into the
+ * Autotuner of the batched launch: time each tile shape and z chunk (4, 5,
+ * 6, 8, 12, 16, 32, 64 and 128 planes) over the whole item list (launches from the current lattices into the
  * spare ones, so the state is unchanged) and keep the fastest.
  * *best_mlups counts the nodes of the cases that are not frozen.
  * Synchronous.

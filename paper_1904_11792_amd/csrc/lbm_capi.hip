@@ -1676,7 +1676,9 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const int zcs[] = {4, 8, 16, 32, 64, 128};
+    // short chunks matter here: the batch's grids are narrow, so their
+    // workgroups are few per case and a chunk of 5-6 planes can beat 8
+    const int zcs[] = {4, 5, 6, 8, 12, 16, 32, 64, 128};
     double best_t = INFINITY;
     const lbm_launch orig = b->launch;
     lbm_launch bl = orig;
