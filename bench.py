@@ -41,7 +41,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_POP = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+# bytes one lattice holds per node (19 populations; the FP32-rest kinds keep
+# the rest population in FP32 and the 18 moving ones in 16 bits)
+BYTES_PER_NODE = {"f64": 152, "f32": 76, "f16s": 38, "bf16s": 38, "f16m": 40, "bf16m": 40}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # The step kernel, and the host code that sets its lattice layout and default
 # launch: a change to any of them invalidates the stored traffic figures.
@@ -69,7 +71,7 @@ def measured_traffic(storage: str, nodes: int):
     return e.get("bytes_per_launch")
 
 
-STORAGE_ID = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+STORAGE_ID = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f16m": 4, "bf16m": 5}
 
 
 def traffic_from_counters(fetch_csv: str, write_csv: str, storage: str) -> dict:
@@ -80,7 +82,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, storage: str) -> dict:
     import csv
 
     spec = __import__("workloads").LARGE_FP32
-    copy_kib = 19 * spec.n * BYTES_PER_POP[storage] / 1024.0
+    copy_kib = spec.n * BYTES_PER_NODE[storage] / 1024.0
     tag = f"k_step<{STORAGE_ID[storage]},"
 
     def per_dispatch(path, counter):
@@ -131,7 +133,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_POP))
+    ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_NODE))
     ap.add_argument("--form", default="single",
                     choices=["single", "batch", "precision", "shift", "convergence", "paper", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -218,7 +220,7 @@ def main():
 
     # plain copy kernel of the same size as one lattice pass (at most that of
     # the 256x256x1024 grid): practical HBM ceiling
-    nbytes = 19 * min(spec.n, workloads.LARGE_FP32.n) * BYTES_PER_POP[args.storage]
+    nbytes = min(spec.n, workloads.LARGE_FP32.n) * BYTES_PER_NODE[args.storage]
     with torch.cuda.stream(stream):
         a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -243,7 +245,7 @@ def main():
     ms_per_step = ms / args.steps
     mlups = spec.n * args.steps / (ms * 1e-3) / 1e6
     d = lat.diagnostics()
-    alg_bytes = 2 * 19 * BYTES_PER_POP[args.storage] * spec.n
+    alg_bytes = 2 * BYTES_PER_NODE[args.storage] * spec.n
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
     traffic = measured_traffic(args.storage, spec.n) if mrt is None else None
     out = {
@@ -276,7 +278,7 @@ def sweep(lat, spec, stream, storage):
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     zcs = (32, 64, 128, 256)
-    bpn = 2 * 19 * BYTES_PER_POP[storage]
+    bpn = 2 * BYTES_PER_NODE[storage]
     print(f"| tile | " + " | ".join(f"z {z} ms" for z in zcs) + " | best GB/s |")
     print("|---|" + "---:|" * (len(zcs) + 1))
     for tx, ty in lbm.lbm_list_tiles():
@@ -342,7 +344,7 @@ def study_precision(args, lbm, workloads, stream):
     for spec in cases:
         rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
         res = {}
-        for storage in ("f64", "f32", "f16s", "bf16s"):
+        for storage in ("f64", "f32", "f16s", "bf16s", "f16m", "bf16m"):
             print(f"# {spec.name} {storage}", file=sys.stderr, flush=True)
             r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, spec.steps, every=10,
                               extra_after=1000)
@@ -639,7 +641,7 @@ def bench_batch(args, lbm, workloads, stream):
                       "live_nodes": nodes},
            "sequential_MLUPS": round(seq_mlups, 1),
            "speedup_vs_sequential": round(mlups / seq_mlups, 3),
-           "roofline": {"bound": "hbm", "achieved": round(2 * 19 * BYTES_PER_POP[args.storage] * nodes *
+           "roofline": {"bound": "hbm", "achieved": round(2 * BYTES_PER_NODE[args.storage] * nodes *
                                                           args.steps / (ms * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s"}}
     out["roofline"]["frac"] = round(out["roofline"]["achieved"] / HBM_PEAK_GBS, 4)

@@ -59,10 +59,21 @@ typedef enum { LBM_PSI_EXP = 0 } lbm_psi;
 
 /*
  * Population storage.  F64 and F32 store f_a as is and compute in the same
- * precision.  F16S and BF16S store the shifted value f_a - w_a rho_ref in
- * IEEE half / bfloat16 (round-to-nearest-even both ways) and compute in FP32.
+ * precision (152 and 76 bytes per node).  F16S and BF16S store the shifted
+ * value f_a - w_a rho_ref of all 19 populations in IEEE half / bfloat16
+ * (round-to-nearest-even both ways) and compute in FP32 (38 bytes per node).
+ * F16M and BF16M store the 18 moving populations the same way and the rest
+ * population, shifted, in FP32 (40 bytes per node); the arithmetic is FP32
+ * on the shifted values, and each collision sets the rest population to the
+ * node's mass minus the moving populations as they are stored, so the
+ * stored mass of a node equals the mass the collision conserves (Eq. 4) to
+ * FP32 rounding instead of moving by 19 half-precision roundings per step.
+ * The FP32-rest kinds run the BGK collision on the run-time tiles
+ * (tile_x = 0) only.
  */
-typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
+typedef enum {
+    LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3, LBM_F16M = 4, LBM_BF16M = 5
+} lbm_storage;
 
 typedef struct {
     int32_t nx, ny, nz; /* grid extents, each >= 1; 19 nx ny and n = nx ny nz <= 2^31 - 1 */
@@ -94,7 +105,8 @@ size_t lbm_workspace_bytes(const lbm_params *p);
 int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
                lbm_ctx **out);
 
-/* Release host-side state and captured graphs.  Never frees the workspace. */
+/* Release host-side state and captured graphs (after waiting for the stream
+ * when a captured graph exists).  Never frees the workspace. */
 int lbm_destroy(lbm_ctx *ctx);
 
 /*
@@ -168,7 +180,8 @@ int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lb
  * tile it is reset to the default launch, and lbm_set_launch then refuses
  * compile-time tiles with UNSUPPORTED.  lbm_init_ligament with rho_l or
  * rho_v <= 0 takes the coexistence densities of the selected collision.
- * Captured graphs are rebuilt.  The batched form uses BGK.
+ * Captured graphs are rebuilt.  The batched form uses BGK.  UNSUPPORTED for
+ * the FP32-rest storage kinds (F16M, BF16M).
  */
 int lbm_set_mrt(lbm_ctx *ctx, const lbm_mrt *mrt);
 
@@ -330,13 +343,31 @@ int lbm_list_tiles(lbm_launch *out, int32_t max, int32_t *count);
 int lbm_default_launch(const lbm_params *p, lbm_launch *out, int32_t *tile_w, int32_t *tile_h);
 
 /*
+ * HBM layout of one lattice for these parameters: rows are grouped in
+ * records of k = *rows_per_record rows, stored [z][y / k][a][y % k][x]
+ * (the 19 population segments of k grid rows contiguous; k = 1 is
+ * row-interleaved [z][y][a][x]), and *lattice_bytes is the size of one
+ * lattice (a context holds two).  k is the smallest power of two whose
+ * segment of k nx elements holds 32 KiB when nx is a power of two from 64 to
+ * 1024 on grids of 2^22 nodes or more (k <= 32), else 2 KiB (k <= 8); k
+ * never exceeds ny (rows beyond ny in the last record are padding).  Either
+ * output may be NULL.
+ * Errors: INVALID_ARG (params as for lbm_workspace_bytes).
+ */
+int lbm_lattice_layout(const lbm_params *p, int32_t *rows_per_record, int64_t *lattice_bytes);
+
+/*
  * Autotuner: time the context's launch, the default launch and each
  * supported tile shape with z chunks of 1, 2, 4, ..., 256 planes on this
- * context's grid (steps_per_candidate launches from the current lattice into the
- * spare one, so the state is unchanged), pick the fastest, set it, and store
- * it in the JSON cache named by the environment variable LBM_TUNE_CACHE (if
- * set) keyed by device architecture, storage and grid.  A later lbm_create
- * with the same key takes the cached shape.  Synchronous.
+ * context's grid, pick the fastest, set it, and store it in the JSON cache
+ * named by the environment variable LBM_TUNE_CACHE (if set) keyed by device
+ * architecture, storage and grid.  Each candidate is timed in the loop
+ * lbm_step runs: 2 ceil(steps_per_candidate / 2) steps alternating between
+ * the two lattices, after two warm-up steps.  The current lattice is copied
+ * to a temporary device buffer first (one lattice, allocated and freed
+ * here) and restored at the end, so the state and the step counter are
+ * unchanged.  A later lbm_create with the same key takes the cached shape
+ * (lbm_get_launch reports it).  Synchronous.
  */
 int lbm_autotune(lbm_ctx *ctx, int32_t steps_per_candidate, lbm_launch *best,
                  double *best_mlups);
@@ -403,10 +434,13 @@ int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
 /*
  * Autotuner of the batched launch: time each tile shape and z chunk (4, 5,
- * 6, 8, 12, 16, 32, 64 and 128 planes) over the whole item list (launches from the current lattices into the
- * spare ones, so the state is unchanged) and keep the fastest.
- * *best_mlups counts the nodes of the cases that are not frozen.
- * Synchronous.
+ * 6, 8, 12, 16, 32, 64 and 128 planes) over the whole item list in the loop
+ * lbm_batch_step runs (an even number of launches alternating between each
+ * case's two lattices, after two warm-up launches) and keep the fastest.
+ * The current lattices of the cases in the launch list are copied to a
+ * temporary device buffer first (allocated and freed here) and restored at
+ * the end, so the state is unchanged.  *best_mlups counts the nodes of the
+ * cases that are not frozen.  Synchronous.
  */
 int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *best,
                        double *best_mlups);

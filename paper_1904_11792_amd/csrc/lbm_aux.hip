@@ -26,29 +26,70 @@ __device__ inline int64_t node_index(int x, int y, int z, int nx, int ny) {
              x += kBlock)                                                            \
             if (const int64_t i = int64_t(row) * (L).nx + x; true)
 
-// Element offset of population a at the lattice site that holds f_a(x, t)
-// under pull streaming: site x - c_a.
+// Offset, in storage elements, of population a at the lattice site that
+// holds f_a(x, t) under pull streaming: site x - c_a.  With an FP32 rest
+// population (kMassRest) population a >= 1 sits in slot a + 1.
+template <int ST>
 __device__ inline int64_t pull_source(int a, int x, int y, int z, const LatticeRef &L) {
-    return a * L.pop_stride + int64_t(wrapi(z - kCZ[a], L.nz)) * L.plane_stride +
+    return pop_slot(a, Storage<ST>::kMassRest) * L.pop_stride + int64_t(wrapi(z - kCZ[a], L.nz)) * L.plane_stride +
            row_offset(wrapi(y - kCY[a], L.ny), L.row_stride, L.rec_shift, L.nx) + wrapi(x - kCX[a], L.nx);
 }
 
-template <int ST>
-__device__ inline double read_pop(const LatticeRef &L, int a, int64_t off) {
-    using Tr = Storage<ST>;
-    using C = typename Tr::C;
-    const auto *p = static_cast<const typename Tr::T *>(L.lat);
-    const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
-    return double(Tr::decode(p[off], shift));
+// Index, in floats, of the FP32 rest population of node (x, y, z)
+// (kMassRest; the rest population does not move).
+__device__ inline int64_t rest_index(int x, int y, int z, const LatticeRef &L) {
+    return int64_t(z) * (L.plane_stride / 2) + row_offset(y, L.row_stride / 2, L.rec_shift, L.nx) + x;
 }
 
 template <int ST>
-__device__ inline void write_pop(const LatticeRef &L, int a, int64_t off, double v) {
+__device__ inline double shift_of(const LatticeRef &L, int a) {
+    using C = typename Storage<ST>::C;
+    return Storage<ST>::kShifted ? double(C(weight(a) * L.rho_ref)) : 0.0;
+}
+
+// f_a(x, t) as FP64.  kMassRest kinds: w_a rho_ref (as the kernels round it
+// to FP32) plus the stored shifted value, added exactly in FP64.
+template <int ST>
+__device__ inline double read_pop(const LatticeRef &L, int a, int x, int y, int z) {
+    using Tr = Storage<ST>;
+    using C = typename Tr::C;
+    if constexpr (Tr::kMassRest) {
+        if (a == 0) return shift_of<ST>(L, 0) + double(static_cast<const float *>(L.lat)[rest_index(x, y, z, L)]);
+        const auto *p = static_cast<const typename Tr::T *>(L.lat);
+        return shift_of<ST>(L, a) + double(static_cast<float>(p[pull_source<ST>(a, x, y, z, L)]));
+    } else {
+        const auto *p = static_cast<const typename Tr::T *>(L.lat);
+        const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
+        return double(Tr::decode(p[pull_source<ST>(a, x, y, z, L)], shift));
+    }
+}
+
+// Store the populations v[a] = f_a(x, t) of one node.  kMassRest kinds round
+// the moving populations to 16 bits and give the rest population what that
+// rounding took from them, so the node keeps its mass to FP32 rounding (and
+// values read by read_pop come back unchanged).
+template <int ST>
+__device__ inline void write_node(const LatticeRef &L, int x, int y, int z, const double (&v)[Q]) {
     using Tr = Storage<ST>;
     using C = typename Tr::C;
     auto *p = static_cast<typename Tr::T *>(L.lat);
-    const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
-    p[off] = Tr::encode(C(v), shift);
+    if constexpr (Tr::kMassRest) {
+        double rest = v[0] - shift_of<ST>(L, 0);
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            const double h = v[a] - shift_of<ST>(L, a);
+            const typename Tr::T stored = Tr::encode(float(h), 0.0f);
+            p[pull_source<ST>(a, x, y, z, L)] = stored;
+            rest += h - double(static_cast<float>(stored));
+        }
+        static_cast<float *>(L.lat)[rest_index(x, y, z, L)] = float(rest);
+    } else {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const C shift = Tr::kShifted ? C(weight(a) * L.rho_ref) : C(0);
+            p[pull_source<ST>(a, x, y, z, L)] = Tr::encode(C(v[a]), shift);
+        }
+    }
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014) used counter-based: first output of
@@ -78,8 +119,10 @@ __global__ __launch_bounds__(kBlock) void k_init_ligament(LatticeRef L, Ligament
             const double U = double(splitmix64(g.seed + uint64_t(i)) >> 11) * (1.0 / 9007199254740992.0);
             rho += g.noise_amp * (2.0 * U - 1.0);
         }
+        double v[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) write_pop<ST>(L, a, pull_source(a, x, y, z, L), weight(a) * rho);
+        for (int a = 0; a < Q; ++a) v[a] = weight(a) * rho;
+        write_node<ST>(L, x, y, z, v);
     }
 }
 
@@ -87,8 +130,10 @@ template <int ST>
 __global__ __launch_bounds__(kBlock) void k_import(LatticeRef L, const double *__restrict__ pop) {
     const int64_t n = int64_t(L.nx) * L.ny * L.nz;
     LBM_FOR_EACH_NODE(L) {
+        double v[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) write_pop<ST>(L, a, pull_source(a, x, y, z, L), pop[a * n + i]);
+        for (int a = 0; a < Q; ++a) v[a] = pop[a * n + i];
+        write_node<ST>(L, x, y, z, v);
     }
 }
 
@@ -97,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_export_pop(LatticeRef L, double *__r
     const int64_t n = int64_t(L.nx) * L.ny * L.nz;
     LBM_FOR_EACH_NODE(L) {
 #pragma unroll
-        for (int a = 0; a < Q; ++a) pop[a * n + i] = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+        for (int a = 0; a < Q; ++a) pop[a * n + i] = read_pop<ST>(L, a, x, y, z);
     }
 }
 
@@ -106,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_export_rho(LatticeRef L, double *__r
     LBM_FOR_EACH_NODE(L) {
         double f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[a] = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+        for (int a = 0; a < Q; ++a) f[a] = read_pop<ST>(L, a, x, y, z);
         rho[i] = density(f);
     }
 }
@@ -137,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_export_force_u(LatticeRef L, const d
             double jx = 0, jy = 0, jz = 0;
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                const double v = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+                const double v = read_pop<ST>(L, a, x, y, z);
                 jx += kCX[a] * v;
                 jy += kCY[a] * v;
                 jz += kCZ[a] * v;
@@ -213,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(LatticeRef L, int axis, int row
             bool finite = true;
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
-                f[a] = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+                f[a] = read_pop<ST>(L, a, x, y, z);
                 finite = finite && isfinite(f[a]);
             }
             const double rho = density(f);
@@ -489,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_init(LatticeRef L, double rho_mid
     LBM_FOR_EACH_NODE(L) {
         double f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[a] = read_pop<ST>(L, a, pull_source(a, x, y, z, L));
+        for (int a = 0; a < Q; ++a) f[a] = read_pop<ST>(L, a, x, y, z);
         const double r = density(f);
         rho[i] = r;
         parent[i] = r > rho_mid ? int32_t(i) : -1;  // NaN is background
@@ -586,7 +631,9 @@ int rows_grid(const LatticeRef &L) {
         case kF64: hipLaunchKernelGGL(KERNEL<kF64>, __VA_ARGS__); break;   \
         case kF32: hipLaunchKernelGGL(KERNEL<kF32>, __VA_ARGS__); break;   \
         case kF16S: hipLaunchKernelGGL(KERNEL<kF16S>, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL(KERNEL<kBF16S>, __VA_ARGS__); break;   \
+        case kBF16S: hipLaunchKernelGGL(KERNEL<kBF16S>, __VA_ARGS__); break; \
+        case kF16M: hipLaunchKernelGGL(KERNEL<kF16M>, __VA_ARGS__); break; \
+        default: hipLaunchKernelGGL(KERNEL<kBF16M>, __VA_ARGS__); break;   \
     }
 
 hipError_t launch_init_ligament(const LatticeRef &L, const LigamentArgs &g, hipStream_t s) {

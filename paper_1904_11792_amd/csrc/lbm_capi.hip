@@ -46,13 +46,16 @@ size_t elem_bytes(int storage) {
     }
 }
 
+bool is_mass_rest(int st) { return st == LBM_F16M || st == LBM_BF16M; }
+
 int validate_params(const lbm_params *p) {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
-    // Offsets within a z plane (19 nx ny populations) and node indices are 32-bit.
+    // Offsets within a z plane (19 nx ny populations, 20 slots per node with
+    // an FP32 rest population) and node indices are 32-bit.
     const int64_t n = int64_t(p->nx) * p->ny * p->nz;
-    if (int64_t(Q) * p->nx * (int64_t(p->ny) + 31) > int64_t(0x7fffffff))
+    if (int64_t(Q + 1) * p->nx * (int64_t(p->ny) + 31) > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane holds more than 2^31 - 1 populations", p->nx, p->ny);
     if (n > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1 nodes", (long long)n);
@@ -62,7 +65,7 @@ int validate_params(const lbm_params *p) {
     if (p->psi != LBM_PSI_EXP) return fail(LBM_ERR_UNSUPPORTED, "psi form %d is not provided", p->psi);
     if (!(p->rho0 > 0.0) || !isfinite(p->rho0))
         return fail(LBM_ERR_INVALID_ARG, "rho0 must be finite and > 0");
-    if (p->storage < LBM_F64 || p->storage > LBM_BF16S)
+    if (p->storage < LBM_F64 || p->storage > LBM_BF16M)
         return fail(LBM_ERR_INVALID_ARG, "unknown storage kind %d", p->storage);
     if (!isfinite(p->rho_ref)) return fail(LBM_ERR_INVALID_ARG, "rho_ref must be finite");
     return LBM_OK;
@@ -107,13 +110,16 @@ Layout layout_of(const lbm_params *p) {
     // Records of k rows, [z][y / k][a][y % k][x]: the 19 population segments
     // of k grid rows are contiguous (population stride k nx, record stride
     // 19 k nx, plane stride 19 nx ny' with ny' = ny rounded up to records).
+    // (kMassRest kinds: 20 slots of 16 bits per node, the FP32 rest
+    // population taking the first two)
     L.rec_shift = record_shift(p->nx, p->ny, p->nz, p->storage);
     const int k = 1 << L.rec_shift;
     const int64_t nyp = padded_rows(p->ny, L.rec_shift);
+    const int slots = storage_slots(is_mass_rest(p->storage));
     L.S = int64_t(k) * p->nx;
-    L.R = Q * k * p->nx;
-    L.P = int(int64_t(Q) * p->nx * nyp);
-    const int64_t cells = int64_t(Q) * p->nx * nyp * p->nz;
+    L.R = slots * k * p->nx;
+    L.P = int(int64_t(slots) * p->nx * nyp);
+    const int64_t cells = int64_t(slots) * p->nx * nyp * p->nz;
     L.lat_bytes = align_up(size_t(cells) * elem_bytes(p->storage), 256);
     L.off_lat1 = L.lat_bytes;
     L.nparts = diag_blocks(p->nx, p->ny, p->nz);
@@ -126,7 +132,7 @@ Layout layout_of(const lbm_params *p) {
     return L;
 }
 
-bool is_shifted(int st) { return st == LBM_F16S || st == LBM_BF16S; }
+bool is_shifted(int st) { return st == LBM_F16S || st == LBM_BF16S || st == LBM_F16M || st == LBM_BF16M; }
 
 std::string arch_name() {
     int dev = 0;
@@ -264,12 +270,14 @@ lbm_launch default_launch(const lbm_params *p) {
     return l;
 }
 
-int check_launch(const lbm_launch *l, int nz) {
+int check_launch(const lbm_launch *l, int storage) {
     if (!l) return fail(LBM_ERR_INVALID_ARG, "launch is NULL");
-    if (find_tile(l->tile_x, l->tile_y) < 0)
-        return fail(LBM_ERR_UNSUPPORTED, "tile %dx%d is not compiled in", l->tile_x, l->tile_y);
+    const int ti = find_tile(l->tile_x, l->tile_y);
+    if (ti < 0) return fail(LBM_ERR_UNSUPPORTED, "tile %dx%d is not compiled in", l->tile_x, l->tile_y);
+    if (!tile_has_storage(ti, storage))
+        return fail(LBM_ERR_UNSUPPORTED, "tile %dx%d is not compiled for storage kind %d (run-time tiles only)",
+                    l->tile_x, l->tile_y, storage);
     if (l->zchunk < 1) return fail(LBM_ERR_INVALID_ARG, "zchunk must be >= 1");
-    (void)nz;
     return LBM_OK;
 }
 
@@ -491,7 +499,7 @@ int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hi
     c->gexec = nullptr;
     c->mrt = MrtParams{};
     lbm_launch l;
-    if (!cache_lookup(tune_key(p), &l) || check_launch(&l, p->nz) != LBM_OK) l = default_launch(p);
+    if (!cache_lookup(tune_key(p), &l) || check_launch(&l, p->storage) != LBM_OK) l = default_launch(p);
     c->launch = l;
     c->tile_index = find_tile(l.tile_x, l.tile_y);
     hipError_t e = launch_fill_u64(c->slices, lay.nslices, 0ull, c->stream);
@@ -505,6 +513,9 @@ int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hi
 
 int lbm_destroy(lbm_ctx *c) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "context is NULL");
+    // A captured graph may still be running on the stream: let it finish
+    // before its executable is destroyed.
+    if (c->gexec) (void)hipStreamSynchronize(c->stream);
     release_graph(c);
     delete c;
     return LBM_OK;
@@ -672,16 +683,16 @@ struct CoexRun {
     }
 };
 
+constexpr int kCoexNodes = 128, kCoexChunk = 1000;
+
 // Advances every run to its end, all unfinished runs in one launch per chunk
-// (one workgroup each).  Synchronous.
-hipError_t run_coexistence(std::vector<CoexRun> &runs) {
-    const int n = 128, chunk = 1000;
+// (one workgroup each).  Synchronous.  Device buffers of the caller: d_state
+// holds 19 * 128 doubles per run, d_out 4 doubles per run, d_cases one
+// table entry per run.
+hipError_t run_coexistence_in(std::vector<CoexRun> &runs, double *d_state, double *d_out, CoexCase *d_cases) {
+    const int n = kCoexNodes, chunk = kCoexChunk;
     const size_t m = runs.size();
-    double *d_state = nullptr, *d_out = nullptr;
-    CoexCase *d_cases = nullptr;
-    hipError_t e = hipMalloc(&d_state, sizeof(double) * Q * n * m);
-    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * 4 * m);
-    if (e == hipSuccess) e = hipMalloc(&d_cases, sizeof(CoexCase) * m);
+    hipError_t e = hipSuccess;
     std::vector<CoexCase> table;
     std::vector<size_t> idx;
     std::vector<double> outs(4 * m);
@@ -711,6 +722,18 @@ hipError_t run_coexistence(std::vector<CoexRun> &runs) {
         if (e == hipSuccess)
             for (size_t j : idx) runs[j].take(&outs[4 * j]);
     }
+    return e;
+}
+
+// The same with temporaries allocated here and freed before returning.
+hipError_t run_coexistence(std::vector<CoexRun> &runs) {
+    const size_t m = runs.size();
+    double *d_state = nullptr, *d_out = nullptr;
+    CoexCase *d_cases = nullptr;
+    hipError_t e = hipMalloc(&d_state, sizeof(double) * Q * kCoexNodes * m);
+    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * 4 * m);
+    if (e == hipSuccess) e = hipMalloc(&d_cases, sizeof(CoexCase) * m);
+    if (e == hipSuccess) e = run_coexistence_in(runs, d_state, d_out, d_cases);
     if (d_cases) (void)hipFree(d_cases);
     if (d_out) (void)hipFree(d_out);
     if (d_state) (void)hipFree(d_state);
@@ -735,22 +758,8 @@ int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, d
     return LBM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
-    return coexistence_impl(G, tau, nullptr, psi, rho0, rho_l, rho_v);
-}
-
-int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, double rho0, double *rho_l,
-                        double *rho_v) {
-    if (!mrt) return fail(LBM_ERR_INVALID_ARG, "mrt is NULL");
-    return coexistence_impl(G, tau, mrt, psi, rho0, rho_l, rho_v);
-}
-
-int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
-                         double rho0, double *rho_l, double *rho_v, int32_t *status) {
+int coexistence_many_impl(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
+                          double rho0, double *rho_l, double *rho_v, int32_t *status) {
     if (m < 1) return fail(LBM_ERR_INVALID_ARG, "m must be >= 1");
     if (!G || !tau || !rho_l || !rho_v || !status) return fail(LBM_ERR_INVALID_ARG, "an array pointer is NULL");
     if (mrt) {
@@ -784,6 +793,25 @@ int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lb
     return LBM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int lbm_coexistence(double G, double tau, int32_t psi, double rho0, double *rho_l, double *rho_v) {
+    return coexistence_impl(G, tau, nullptr, psi, rho0, rho_l, rho_v);
+}
+
+int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, double rho0, double *rho_l,
+                        double *rho_v) {
+    if (!mrt) return fail(LBM_ERR_INVALID_ARG, "mrt is NULL");
+    return coexistence_impl(G, tau, mrt, psi, rho0, rho_l, rho_v);
+}
+
+int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
+                         double rho0, double *rho_l, double *rho_v, int32_t *status) {
+    return coexistence_many_impl(m, G, tau, mrt, psi, rho0, rho_l, rho_v, status);
+}
+
 int lbm_set_mrt(lbm_ctx *c, const lbm_mrt *mrt) {
     int st = check_ctx(c);
     if (st != LBM_OK) return st;
@@ -791,6 +819,8 @@ int lbm_set_mrt(lbm_ctx *c, const lbm_mrt *mrt) {
         st = check_mrt(mrt);
         if (st != LBM_OK) return st;
     }
+    if (mrt && is_mass_rest(c->p.storage))
+        return fail(LBM_ERR_UNSUPPORTED, "the MRT collision is not provided for the FP32-rest storage kinds");
     c->mrt = mrt_params(mrt);
     if (c->mrt.on && !tile_has_mrt(c->tile_index)) {
         c->launch = default_launch(&c->p);  // a run-time tile, which has the MRT kernel
@@ -1029,7 +1059,7 @@ int lbm_get_step(const lbm_ctx *c, int64_t *step) {
 int lbm_set_launch(lbm_ctx *c, const lbm_launch *l) {
     int st = check_ctx(c);
     if (st != LBM_OK) return st;
-    st = check_launch(l, c->p.nz);
+    st = check_launch(l, c->p.storage);
     if (st != LBM_OK) return st;
     if (c->mrt.on && !tile_has_mrt(find_tile(l->tile_x, l->tile_y)))
         return fail(LBM_ERR_UNSUPPORTED, "the MRT collision runs on the run-time tiles (tile_x = 0) only");
@@ -1067,14 +1097,20 @@ int lbm_default_launch(const lbm_params *p, lbm_launch *out, int32_t *tile_w, in
     return LBM_OK;
 }
 
+int lbm_lattice_layout(const lbm_params *p, int32_t *rows_per_record, int64_t *lattice_bytes) {
+    const int st = validate_params(p);
+    if (st != LBM_OK) return st;
+    const Layout L = layout_of(p);
+    if (rows_per_record) *rows_per_record = int32_t(1) << L.rec_shift;
+    if (lattice_bytes) *lattice_bytes = int64_t(L.lat_bytes);
+    return LBM_OK;
+}
+
 int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, double *best_mlups) {
     int st = check_ctx(c);
     if (st != LBM_OK) return st;
     if (!c->initialized) return fail(LBM_ERR_STATE, "lattice not initialised");
     if (steps_per_candidate < 1) return fail(LBM_ERR_INVALID_ARG, "steps_per_candidate must be >= 1");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
     // Candidates: the context's launch, the default launch, then every
     // compiled tile with z chunks of 1 to 256 planes.
     std::vector<lbm_launch> cands{c->launch, default_launch(&c->p)};
@@ -1089,27 +1125,49 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_candidate, lbm_launch *best, doub
             cands.push_back(l);
         }
     }
+    // Each candidate is timed in the loop lbm_step runs: steps alternate
+    // between the two lattices (an even number, so every candidate starts
+    // and ends on the current one).  The state is saved to a temporary copy
+    // first and restored at the end.
+    const int pairs = (steps_per_candidate + 1) / 2;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void *saved = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMalloc(&saved, c->lay.lat_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(saved, c->lat[c->cur], c->lay.lat_bytes, hipMemcpyDeviceToDevice, c->stream);
     double best_t = INFINITY;
     lbm_launch bl = c->launch;
     const double nodes = double(c->p.nx) * c->p.ny * c->p.nz;
     for (const lbm_launch &l : cands) {
+        if (e != hipSuccess) break;
         const int ti = find_tile(l.tile_x, l.tile_y);
-        if (ti < 0 || (c->mrt.on && !tile_has_mrt(ti))) continue;
-        const StepArgs A = step_args(c, l, c->cur);  // cur -> spare: state untouched
-        e = launch_step(ti, c->p.storage, A, c->stream);  // warm-up
+        if (ti < 0 || (c->mrt.on && !tile_has_mrt(ti)) || !tile_has_storage(ti, c->p.storage)) continue;
+        const StepArgs A = step_args(c, l, c->cur), B = step_args(c, l, c->cur ^ 1);
+        auto two_steps = [&]() {
+            hipError_t r = launch_step(ti, c->p.storage, A, c->stream);
+            if (r == hipSuccess) r = launch_step(ti, c->p.storage, B, c->stream);
+            return r;
+        };
+        e = two_steps();  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
-            e = launch_step(ti, c->p.storage, A, c->stream);
+        for (int s = 0; s < pairs && e == hipSuccess; ++s) e = two_steps();
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) break;
-        const double t = ms / steps_per_candidate;
+        const double t = ms / (2.0 * pairs);
         if (t < best_t) {
             best_t = t;
             bl = l;
         }
+    }
+    if (saved) {
+        hipError_t r = hipMemcpyAsync(c->lat[c->cur], saved, c->lay.lat_bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = r;
+        (void)hipFree(saved);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1499,6 +1557,7 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
 
 int lbm_batch_destroy(lbm_batch *b) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (b->gexec) (void)hipStreamSynchronize(b->stream);
     batch_release_graph(b);
     if (b->ev_frozen) (void)hipEventDestroy(b->ev_frozen);
     if (b->h_frozen) (void)hipHostFree(b->h_frozen);
@@ -1658,7 +1717,7 @@ int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l) {
     int st = batch_check(b);
     if (st != LBM_OK) return st;
-    st = check_launch(l, 1);
+    st = check_launch(l, b->p[0].storage);
     if (st != LBM_OK) return st;
     if (l->zchunk < kBatchMinZchunk) return fail(LBM_ERR_INVALID_ARG, "batched zchunk must be >= %d", kBatchMinZchunk);
     b->launch = *l;
@@ -1673,17 +1732,34 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     if (st != LBM_OK) return st;
     if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
     if (steps_per_candidate < 1) return fail(LBM_ERR_INVALID_ARG, "steps_per_candidate must be >= 1");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
     // short chunks matter here: the batch's grids are narrow, so their
     // workgroups are few per case and a chunk of 5-6 planes can beat 8
     const int zcs[] = {4, 5, 6, 8, 12, 16, 32, 64, 128};
-    double best_t = INFINITY;
     const lbm_launch orig = b->launch;
     lbm_launch bl = orig;
-    // throughput is counted over the cases that are not frozen (frozen ones exit at once)
+    double best_t = INFINITY;
+    // Candidates are timed in the loop lbm_batch_step runs: launches that
+    // alternate between the two lattices of every case (an even number).
+    // The current lattices of the cases in the launch list are saved first
+    // and restored at the end; frozen cases are not touched by the step.
+    std::vector<int> live;
+    size_t save_bytes = 0;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->dropped[i]) {
+            live.push_back(i);
+            save_bytes += b->lay[i].lat_bytes;
+        }
     std::vector<int32_t> fz(b->n, 0);
+    const int pairs = (steps_per_candidate + 1) / 2;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    char *saved = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess && save_bytes) e = hipMalloc(reinterpret_cast<void **>(&saved), save_bytes);
+    for (size_t k = 0, off = 0; k < live.size() && e == hipSuccess; off += b->lay[live[k]].lat_bytes, ++k)
+        e = hipMemcpyAsync(saved + off, case_lat(b, live[k], b->parity), b->lay[live[k]].lat_bytes,
+                           hipMemcpyDeviceToDevice, b->stream);
+    // throughput is counted over the cases that are not frozen (frozen ones exit at once)
     if (e == hipSuccess)
         e = hipMemcpyAsync(fz.data(), b->d_frozen, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1691,6 +1767,7 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     for (int i = 0; i < b->n; ++i)
         if (fz[i] == 0) nodes += double(b->p[i].nx) * b->p[i].ny * b->p[i].nz;
     for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
+        if (!tile_has_storage(ti, b->p[0].storage)) continue;
         lbm_launch l;
         tile_shape(ti, &l.tile_x, &l.tile_y);
         for (int zc : zcs) {
@@ -1702,24 +1779,37 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
                 if (e == hipErrorInvalidValue) e = hipSuccess;  // more items than the table holds
                 continue;
             }
-            // launches from the current lattice into the spare one: state unchanged
-            e = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
-                                  b->parity, b->stream);
+            auto two_steps = [&]() {
+                hipError_t r = hipSuccess;
+                if (b->nitems > 0)
+                    for (int q = 0; q < 2 && r == hipSuccess; ++q)
+                        r = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
+                                              b->d_frozen, b->parity ^ q, b->stream);
+                return r;
+            };
+            e = two_steps();  // warm-up
             if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            for (int s = 0; s < steps_per_candidate && e == hipSuccess; ++s)
-                e = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
-                                      b->parity, b->stream);
+            for (int s = 0; s < pairs && e == hipSuccess; ++s) e = two_steps();
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
-            const double t = ms / steps_per_candidate;
+            const double t = ms / (2.0 * pairs);
             if (t < best_t) {
                 best_t = t;
                 bl = l;
             }
         }
+    }
+    if (saved) {
+        hipError_t r = hipSuccess;
+        for (size_t k = 0, off = 0; k < live.size() && r == hipSuccess; off += b->lay[live[k]].lat_bytes, ++k)
+            r = hipMemcpyAsync(case_lat(b, live[k], b->parity), saved + off, b->lay[live[k]].lat_bytes,
+                               hipMemcpyDeviceToDevice, b->stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(b->stream);
+        if (e == hipSuccess) e = r;
+        (void)hipFree(saved);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -25,39 +25,69 @@ __host__ __device__ constexpr double weight(int a) {
     return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-enum StorageKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+enum StorageKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF16M = 4, kBF16M = 5 };
+constexpr int kNumStorage = 6;
 
 // Storage traits: T is what lives in HBM, C what the arithmetic uses.
 // Shifted kinds hold f_a - w_a rho_ref, rounded to nearest even.
+//
+// kMassRest (F16M, BF16M): the 18 moving populations are stored shifted in
+// 16 bits and the rest population, shifted, in FP32; the arithmetic works on
+// the shifted values h_a = f_a - w_a rho_ref themselves (decode returns h_a),
+// and the collision sets the rest population from the node's mass minus the
+// moving populations as they are stored (collide_shifted).  A node's stored
+// mass then equals the mass the collision conserves to FP32 rounding, where
+// with every population in 16 bits it moved by up to 19 half-precision
+// roundings per step, one-signed wherever the values repeat from step to step.
 template <int ST> struct Storage;
 template <> struct Storage<kF64> {
     using T = double;
     using C = double;
-    static constexpr bool kShifted = false;
+    static constexpr bool kShifted = false, kMassRest = false;
     __device__ static C decode(T v, C) { return v; }
     __device__ static T encode(C f, C) { return f; }
 };
 template <> struct Storage<kF32> {
     using T = float;
     using C = float;
-    static constexpr bool kShifted = false;
+    static constexpr bool kShifted = false, kMassRest = false;
     __device__ static C decode(T v, C) { return v; }
     __device__ static T encode(C f, C) { return f; }
 };
 template <> struct Storage<kF16S> {
     using T = _Float16;
     using C = float;
-    static constexpr bool kShifted = true;
+    static constexpr bool kShifted = true, kMassRest = false;
     __device__ static C decode(T v, C shift) { return shift + static_cast<float>(v); }
     __device__ static T encode(C f, C shift) { return static_cast<_Float16>(f - shift); }
 };
 template <> struct Storage<kBF16S> {
     using T = __bf16;
     using C = float;
-    static constexpr bool kShifted = true;
+    static constexpr bool kShifted = true, kMassRest = false;
     __device__ static C decode(T v, C shift) { return shift + static_cast<float>(v); }
     __device__ static T encode(C f, C shift) { return static_cast<__bf16>(f - shift); }
 };
+template <> struct Storage<kF16M> {
+    using T = _Float16;
+    using C = float;
+    static constexpr bool kShifted = true, kMassRest = true;
+    __device__ static C decode(T v, C) { return static_cast<float>(v); }
+    __device__ static T encode(C h, C) { return static_cast<_Float16>(h); }
+};
+template <> struct Storage<kBF16M> {
+    using T = __bf16;
+    using C = float;
+    static constexpr bool kShifted = true, kMassRest = true;
+    __device__ static C decode(T v, C) { return static_cast<float>(v); }
+    __device__ static T encode(C h, C) { return static_cast<__bf16>(h); }
+};
+
+// Slots of 16-bit elements per node and population index -> slot: with an
+// FP32 rest population the rest takes two slots (0 and 1) and population
+// a >= 1 sits in slot a + 1.
+__host__ __device__ constexpr int storage_slots(bool mass_rest) { return mass_rest ? Q + 1 : Q; }
+__host__ __device__ constexpr int pop_slot(int a, bool mass_rest) { return (mass_rest && a > 0) ? a + 1 : a; }
 
 __device__ inline float expm1_c(float v) { return expm1f(v); }
 __device__ inline double expm1_c(double v) { return expm1(v); }
@@ -139,6 +169,66 @@ __device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
 #pragma unroll
     for (int a = 2; a < Q; ++a) moving += f[a];
     f[0] = rho - moving;
+}
+
+// The same BGK relaxation for the shifted variables h_a = f_a - w_a rho_ref
+// of the kMassRest storage kinds.  m = rho - rho_ref is the sum of the h_a
+// (the 18 stored 16-bit values first, whose FP32 sum is exact unless their
+// magnitudes span more than 24 bits, then the FP32 rest); j = sum c_a h_a
+// (sum_a c_a w_a = 0); the equilibrium minus the shift is
+// w_a (m + rho (4.5 (c.u')^2 - 1.5 u'^2)) +- 3 w_a rho c.u'.  The moving
+// populations leave rounded to the storage type (`out`, slots 1..18); the
+// rest population becomes m minus their exact FP32 sum, so the node's stored
+// mass is m to within one FP32 rounding.
+template <typename Tr>
+__device__ inline float shifted_excess(const float (&h)[Q]) {
+    float s = h[1];
+#pragma unroll
+    for (int a = 2; a < Q; ++a) s += h[a];
+    return s + h[0];
+}
+
+template <typename Tr>
+__device__ inline void collide_shifted(float (&h)[Q], typename Tr::T (&out)[Q], float Fx, float Fy, float Fz,
+                                       float tau, float omega, float rho_ref) {
+    using C = float;
+    const C m = shifted_excess<Tr>(h);
+    const C rho = rho_ref + m;
+    const C jx = (h[1] - h[2]) + (h[7] - h[8]) + (h[9] - h[10]) + (h[11] - h[12]) + (h[13] - h[14]);
+    const C jy = (h[3] - h[4]) + (h[7] - h[8]) - (h[9] - h[10]) + (h[15] - h[16]) + (h[17] - h[18]);
+    const C jz = (h[5] - h[6]) + (h[11] - h[12]) - (h[13] - h[14]) + (h[15] - h[16]) - (h[17] - h[18]);
+    const C inv = C(1) / rho;
+    const C ux = (jx + tau * Fx) * inv;
+    const C uy = (jy + tau * Fy) * inv;
+    const C uz = (jz + tau * Fz) * inv;
+    const C q = C(-1.5) * (ux * ux + uy * uy + uz * uz);
+#define LBM_SPAIR(A, CU, W)                                          \
+    {                                                                \
+        const C cu = (CU);                                           \
+        const C wr = C(W) * rho;                                     \
+        const C sym = C(W) * m + wr * (q + C(4.5) * cu * cu);        \
+        const C asym = wr * C(3) * cu;                               \
+        h[A] += omega * ((sym + asym) - h[A]);                       \
+        h[A + 1] += omega * ((sym - asym) - h[A + 1]);               \
+    }
+    LBM_SPAIR(1, ux, 1.0 / 18.0)
+    LBM_SPAIR(3, uy, 1.0 / 18.0)
+    LBM_SPAIR(5, uz, 1.0 / 18.0)
+    LBM_SPAIR(7, ux + uy, 1.0 / 36.0)
+    LBM_SPAIR(9, ux - uy, 1.0 / 36.0)
+    LBM_SPAIR(11, ux + uz, 1.0 / 36.0)
+    LBM_SPAIR(13, ux - uz, 1.0 / 36.0)
+    LBM_SPAIR(15, uy + uz, 1.0 / 36.0)
+    LBM_SPAIR(17, uy - uz, 1.0 / 36.0)
+#undef LBM_SPAIR
+    C moving = 0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        out[a] = Tr::encode(h[a], C(0));
+        const C r = static_cast<C>(out[a]);
+        moving = (a == 1) ? r : moving + r;
+    }
+    h[0] = m - moving;
 }
 
 // ---------------------------------------------------------------------------

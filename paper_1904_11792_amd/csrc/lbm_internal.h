@@ -117,6 +117,9 @@ int find_tile(int tx, int ty);
 // (tile_has_mrt).
 hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s);
 bool tile_has_mrt(int tile_index);
+// Whether this tile's step kernel is compiled for the storage kind (the
+// FP32-rest kinds are compiled for the run-time tiles only).
+bool tile_has_storage(int tile_index, int storage);
 // Workgroups of this tile's step kernel that the device runs at once (compute
 // units x resident workgroups per unit); 0 if the runtime cannot say.
 int launch_slots(int tile_index, int storage);

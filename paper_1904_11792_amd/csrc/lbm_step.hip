@@ -65,9 +65,20 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     MrtRates<C> rates;
     if constexpr (MRT)
         rates = mrt_rates<C>(1.0 / A.tau, A.mrt.s_e, A.mrt.s_eps, A.mrt.s_q, A.mrt.s_pi, A.mrt.s_m, A.mrt.s_j);
+    constexpr bool MR = Tr::kMassRest;
+    static_assert(!(MRT && MR), "the MRT collision is not provided for the FP32-rest storage kinds");
     C shift[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) shift[a] = Tr::kShifted ? C(weight(a) * A.rho_ref) : C(0);
+    const C rho_ref = C(A.rho_ref);
+    // density of a node from its (decoded) populations; with kMassRest the
+    // values are h_a and the density is rho_ref + sum h_a
+    auto node_density = [&](const C(&f)[Q]) -> C {
+        if constexpr (MR)
+            return rho_ref + shifted_excess<Tr>(f);
+        else
+            return density(f);
+    };
 
     const int x0 = tile_x * TX, y0 = tile_y * TY;
     const int z0 = chunk * A.zchunk;
@@ -87,6 +98,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int rsh = A.rec_shift;
     const int Y[3] = {row_offset(wrapi(gy - 1, ny), rowst, rsh, nx), row_offset(gy, rowst, rsh, nx),
                       row_offset(wrapi(gy + 1, ny), rowst, rsh, nx)};
+    // kMassRest: FP32 rest population, indexed in floats from the plane base
+    // (records of rowst 16-bit slots are rowst / 2 floats apart)
+    const int YR = MR ? row_offset(gy, rowst / 2, rsh, nx) : 0;
 
     // Ring node handled by this thread (t < RING), in tile coordinates [-1, TX] x [-1, TY].
     const bool ring = t < RING;
@@ -106,16 +120,18 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int RX[3] = {wrapi(rgx - 1, nx), rgx, wrapi(rgx + 1, nx)};
     const int RY[3] = {row_offset(wrapi(rgy - 1, ny), rowst, rsh, nx), row_offset(rgy, rowst, rsh, nx),
                        row_offset(wrapi(rgy + 1, ny), rowst, rsh, nx)};
+    const int RYR = MR ? row_offset(rgy, rowst / 2, rsh, nx) : 0;
 
     // The plane offset is 64-bit and wave-uniform; the offset within a plane
     // is 32-bit (the host keeps 19 nx ny below 2^31).
-    auto gather = [&](int zc, const int(&XX)[3], const int(&YY)[3], C(&f)[Q]) {
+    auto gather = [&](int zc, const int(&XX)[3], const int(&YY)[3], int YYR, C(&f)[Q]) {
         const T *Zp[3] = {src + wrapi(zc - 1, nz) * plane, src + zc * plane, src + wrapi(zc + 1, nz) * plane};
         // Opaque copies of the row offsets: without them the compiler keeps
         // 19 loop-invariant 64-bit addresses per thread (38 VGPRs) across the
         // march instead of forming each address at its load.
-        int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
+        int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]}, yr = YYR;
         asm volatile("" : "+v"(yy[0]), "+v"(yy[1]), "+v"(yy[2]), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]));
+        if constexpr (MR) asm volatile("" : "+v"(yr));
         // All 19 loads are issued before the first use: the scheduler would
         // otherwise interleave load, wait and convert for 16-bit storage.
         // With PRIO the wave issues them at raised priority, ahead of other
@@ -124,24 +140,30 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         // FP64 unchanged; the batched launch, whose workgroups belong to
         // many small grids, 3-5% slower, so it keeps the default priority.
         T raw[Q];
+        float rest = 0.0f;
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) raw[a] = (Zp[1 - kCZ[a]] + a * S)[yy[1 - kCY[a]] + xx[1 - kCX[a]]];
+        for (int a = 0; a < Q; ++a) {
+            if (MR && a == 0)
+                rest = reinterpret_cast<const float *>(Zp[1])[yr + xx[1]];
+            else
+                raw[a] = (Zp[1 - kCZ[a]] + pop_slot(a, MR) * S)[yy[1 - kCY[a]] + xx[1 - kCX[a]]];
+        }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[a] = Tr::decode(raw[a], shift[a]);
+        for (int a = 0; a < Q; ++a) f[a] = (MR && a == 0) ? C(rest) : Tr::decode(raw[a], shift[a]);
     };
     // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
     auto load_plane = [&](int zc, int s, C(&f)[Q]) {
         if (inside) {
-            gather(zc, X, Y, f);
-            W(s, ly + 1, lx + 1) = pseudo_potential(density(f), rho0, inv_rho0);
+            gather(zc, X, Y, YR, f);
+            W(s, ly + 1, lx + 1) = pseudo_potential(node_density(f), rho0, inv_rho0);
         }
         if (ring) {
             C g[Q];
-            gather(zc, RX, RY, g);
-            W(s, ry + 1, rx + 1) = pseudo_potential(density(g), rho0, inv_rho0);
+            gather(zc, RX, RY, RYR, g);
+            W(s, ry + 1, rx + 1) = pseudo_potential(node_density(g), rho0, inv_rho0);
         }
     };
 
@@ -165,16 +187,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         };
         C Fx, Fy, Fz;
         sc_force<C>(W(s0, ly + 1, lx + 1), G, P, Fx, Fy, Fz);
-        if constexpr (MRT)
-            collide_mrt<C>(f, Fx, Fy, Fz, rates);
-        else
-            collide<C>(f, Fx, Fy, Fz, tau, omega);
         T *const zb = dst + zc * plane;
         int o = Y[1] + X[1];
-        asm volatile("" : "+v"(o));  // as in gather: form each store address here
+        if constexpr (MR) {
+            T out[Q];
+            collide_shifted<Tr>(f, out, Fx, Fy, Fz, tau, omega, rho_ref);
+            int orr = YR + X[1];
+            asm volatile("" : "+v"(o), "+v"(orr));  // as in gather: form each store address here
+            __builtin_nontemporal_store(f[0], &reinterpret_cast<float *>(zb)[orr]);
 #pragma unroll
-        for (int a = 0; a < Q; ++a)
-            __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), &(zb + a * S)[o]);
+            for (int a = 1; a < Q; ++a) __builtin_nontemporal_store(out[a], &(zb + pop_slot(a, MR) * S)[o]);
+        } else {
+            if constexpr (MRT)
+                collide_mrt<C>(f, Fx, Fy, Fz, rates);
+            else
+                collide<C>(f, Fx, Fy, Fz, tau, omega);
+            asm volatile("" : "+v"(o));  // as in gather: form each store address here
+#pragma unroll
+            for (int a = 0; a < Q; ++a)
+                __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), &(zb + a * S)[o]);
+        }
     };
 
     C cur[Q], nxt[Q];
@@ -191,11 +223,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 }
 
 template <int ST, int TX, int TY, bool MRT>
-__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step(StepArgs A) {
+__device__ __forceinline__ void step_grid(const StepArgs &A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
     step_tile<ST, TX, TY, MRT, true>(A, tile % A.tiles_x, tile / A.tiles_x, chunk);
+}
+
+template <int ST, int TX, int TY>
+__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_bgk(StepArgs A) {
+    step_grid<ST, TX, TY, false>(A);
+}
+
+template <int ST, int TX, int TY>
+__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_mrt(StepArgs A) {
+    step_grid<ST, TX, TY, true>(A);
 }
 
 // Batched form: one launch covers every case's work items.  Items are
@@ -221,30 +263,36 @@ __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_batch(const BatchCas
 
 struct TileEntry {
     int tx, ty;
-    const void *fn[4];
-    const void *batch_fn[4];
-    const void *mrt_fn[4];  // MRT collision: run-time tiles only
+    const void *fn[kNumStorage];
+    const void *batch_fn[kNumStorage];
+    const void *mrt_fn[kNumStorage];  // MRT collision: run-time tiles, storages 0-3 only
 };
 
-#define LBM_TILE_FNS(TXV, TYV)                                                                      \
-    {(const void *)k_step<kF64, TXV, TYV, false>, (const void *)k_step<kF32, TXV, TYV, false>,     \
-     (const void *)k_step<kF16S, TXV, TYV, false>, (const void *)k_step<kBF16S, TXV, TYV, false>}, \
-    {(const void *)k_step_batch<kF64, TXV, TYV>, (const void *)k_step_batch<kF32, TXV, TYV>,        \
-     (const void *)k_step_batch<kF16S, TXV, TYV>, (const void *)k_step_batch<kBF16S, TXV, TYV>}
-#define LBM_TILE(TXV, TYV) {TXV, TYV, LBM_TILE_FNS(TXV, TYV), {nullptr, nullptr, nullptr, nullptr}}
-#define LBM_TILE_MRT(TXV, TYV)                                                                     \
-    {TXV, TYV, LBM_TILE_FNS(TXV, TYV),                                                             \
-     {(const void *)k_step<kF64, TXV, TYV, true>, (const void *)k_step<kF32, TXV, TYV, true>,      \
-      (const void *)k_step<kF16S, TXV, TYV, true>, (const void *)k_step<kBF16S, TXV, TYV, true>}}
+// Every tile has the four storage kinds of the first round of kernels; the
+// FP32-rest kinds (F16M, BF16M) are compiled for the run-time tiles only.
+#define LBM_TILE_FNS4(K, TXV, TYV) \
+    (const void *)K<kF64, TXV, TYV>, (const void *)K<kF32, TXV, TYV>, (const void *)K<kF16S, TXV, TYV>, \
+        (const void *)K<kBF16S, TXV, TYV>
+#define LBM_TILE(TXV, TYV)                                                                          \
+    {TXV, TYV, {LBM_TILE_FNS4(k_step_bgk, TXV, TYV), nullptr, nullptr},                             \
+     {LBM_TILE_FNS4(k_step_batch, TXV, TYV), nullptr, nullptr},                                     \
+     {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}}
+#define LBM_TILE_RT(TXV, TYV)                                                                       \
+    {TXV, TYV,                                                                                      \
+     {LBM_TILE_FNS4(k_step_bgk, TXV, TYV), (const void *)k_step_bgk<kF16M, TXV, TYV>,              \
+      (const void *)k_step_bgk<kBF16M, TXV, TYV>},                                                  \
+     {LBM_TILE_FNS4(k_step_batch, TXV, TYV), (const void *)k_step_batch<kF16M, TXV, TYV>,          \
+      (const void *)k_step_batch<kBF16M, TXV, TYV>},                                                \
+     {LBM_TILE_FNS4(k_step_mrt, TXV, TYV), nullptr, nullptr}}
 
 // Entries (0, 512) and (0, 1024) are the run-time shaped tiles.
 static const TileEntry kTiles[] = {
-    LBM_TILE_MRT(0, 512), LBM_TILE_MRT(0, 1024), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
+    LBM_TILE_RT(0, 512), LBM_TILE_RT(0, 1024), LBM_TILE(256, 4), LBM_TILE(128, 8), LBM_TILE(128, 4), LBM_TILE(64, 16), LBM_TILE(64, 8),
     LBM_TILE(64, 4), LBM_TILE(32, 16), LBM_TILE(32, 8), LBM_TILE(16, 16),
 };
 #undef LBM_TILE
-#undef LBM_TILE_MRT
-#undef LBM_TILE_FNS
+#undef LBM_TILE_RT
+#undef LBM_TILE_FNS4
 
 // Width: nx split into the fewest tiles of at most the cap, as evenly as
 // possible, so that the tiles carry equal work (a 24-wide remainder tile beside
@@ -278,11 +326,13 @@ int find_tile(int tx, int ty) {
 }
 
 bool tile_has_mrt(int tile_index) { return kTiles[tile_index].mrt_fn[0] != nullptr; }
+bool tile_has_storage(int tile_index, int storage) { return kTiles[tile_index].fn[storage] != nullptr; }
 
 int launch_slots(int tile_index, int storage) {
     const TileEntry &e = kTiles[tile_index];
     const int threads = e.tx ? e.tx * e.ty : e.ty;
     int dev = 0, cus = 0, per_cu = 0;
+    if (!e.fn[storage]) return 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e.fn[storage], threads, 0) != hipSuccess)
@@ -305,6 +355,7 @@ hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases
                              const int4 *items, int nitems, const int32_t *frozen, int parity,
                              hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
+    if (!e.batch_fn[storage]) return hipErrorInvalidDeviceFunction;
     void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity};
     const int threads = e.tx ? e.tx * e.ty : e.ty;
     return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(threads), kargs, 0, s);

@@ -36,11 +36,12 @@ LBM_ERR_STATE = -4
 LBM_ERR_DIVERGED = -5
 LBM_ERR_BUFFER_TOO_SMALL = -6
 LBM_PSI_EXP = 0
-LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
+LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F16M, LBM_BF16M = 0, 1, 2, 3, 4, 5
 LBM_FIELD_RHO, LBM_FIELD_U, LBM_FIELD_FORCE, LBM_FIELD_POP = 1, 2, 4, 8
 LBM_DIAG_RING = 4096
 
-STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
+STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
+           "f16m": LBM_F16M, "bf16m": LBM_BF16M}
 Q = 19
 
 
@@ -123,6 +124,7 @@ _SIGS = {
     "lbm_get_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_list_tiles": (ctypes.c_int, [_P(lbm_launch), _i32, _P(_i32)]),
     "lbm_default_launch": (ctypes.c_int, [_P(lbm_params), _P(lbm_launch), _P(_i32), _P(_i32)]),
+    "lbm_lattice_layout": (ctypes.c_int, [_P(lbm_params), _P(_i32), _P(_i64)]),
     "lbm_autotune": (ctypes.c_int, [_vp, _i32, _P(lbm_launch), _P(_d)]),
     "lbm_set_graph_chunk": (ctypes.c_int, [_vp, _i32]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -200,6 +202,10 @@ def lbm_coexistence_many(G, tau, psi: int = LBM_PSI_EXP, rho0: float = 1.0, mrt:
 
     Returns (rho_l, rho_v, status) as numpy arrays; a diverged run has status
     LBM_ERR_DIVERGED and NaN densities (no exception for that)."""
+    return _coexistence_many(_lib.lbm_coexistence_many, G, tau, psi, rho0, mrt)
+
+
+def _coexistence_many(fn, G, tau, psi, rho0, mrt):
     G = np.ascontiguousarray(G, dtype=np.float64)
     tau = np.ascontiguousarray(tau, dtype=np.float64)
     if G.shape != tau.shape or G.ndim != 1:
@@ -209,8 +215,8 @@ def lbm_coexistence_many(G, tau, psi: int = LBM_PSI_EXP, rho0: float = 1.0, mrt:
     st = np.empty(m, dtype=np.int32)
     dp = lambda a: a.ctypes.data_as(_P(_d))
     mp = ctypes.byref(make_mrt(**mrt)) if mrt is not None else None
-    _check(_lib.lbm_coexistence_many(m, dp(G), dp(tau), mp, psi, rho0, dp(rl), dp(rv),
-                                     st.ctypes.data_as(_P(_i32))), ok=(LBM_OK, LBM_ERR_DIVERGED))
+    _check(fn(m, dp(G), dp(tau), mp, psi, rho0, dp(rl), dp(rv), st.ctypes.data_as(_P(_i32))),
+           ok=(LBM_OK, LBM_ERR_DIVERGED))
     return rl, rv, st
 
 
@@ -302,6 +308,13 @@ def lbm_default_launch(params: lbm_params):
     return (l.tile_x, l.tile_y, l.zchunk), (tw.value, th.value)
 
 
+def lbm_lattice_layout(params: lbm_params) -> tuple[int, int]:
+    """(rows per record, bytes of one lattice) of the HBM layout for these parameters."""
+    k, nbytes = _i32(), _i64()
+    _check(_lib.lbm_lattice_layout(ctypes.byref(params), ctypes.byref(k), ctypes.byref(nbytes)))
+    return k.value, nbytes.value
+
+
 def lbm_autotune(ctx, steps_per_candidate: int = 5):
     l = lbm_launch()
     m = _d()
@@ -351,6 +364,9 @@ class Lattice:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        # the library works on the workspace on self.stream: the caching
+        # allocator must not hand it out again before that work is done
+        self.workspace.record_stream(self.stream)
         self.ctx = lbm_create(self.params, self.workspace.data_ptr(), nbytes,
                               _stream_handle(self.stream))
         self.shape = (nz, ny, nx)
@@ -364,6 +380,7 @@ class Lattice:
 
     def close(self):
         if getattr(self, "ctx", None):
+            self.stream.synchronize()  # queued steps still use the workspace
             lbm_destroy(self.ctx)
             self.ctx = None
 
@@ -471,6 +488,7 @@ class Batch:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self.workspace.record_stream(self.stream)  # as in Lattice
         h = _vp()
         _check(_lib.lbm_batch_create(n, arr, _vp(self.workspace.data_ptr()), nbytes,
                                      _vp(_stream_handle(self.stream)), ctypes.byref(h)))
@@ -480,6 +498,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "handle", None):
+            self.stream.synchronize()
             _check(_lib.lbm_batch_destroy(self.handle))
             self.handle = None
 

@@ -1,0 +1,99 @@
+"""The batched form against the FP64 oracle.
+
+Each case of a batch is the update of Eq. (3) with the shift of Eq. (6)
+(Section 2) on its own grid, with its own tau, G and densities taken from
+the device case table.  Here nine cases of the 64-ligament workload
+(uneven grids 24^2 x 58 ... 38^2 x 113, tau 0.64 ... 1.13, G -5.94 ... -5.05;
+cases the oracle finds stable over 200 steps)
+plus one case that diverges within a few steps run through lbm_batch_* at
+the launches the benchmark uses (512-thread run-time tiles, z chunks of 6
+and 8 planes), in captured graphs of 20 steps.  After 100 steps the
+diagnostics freeze the diverged case and drop it from the launch list
+(the item list and the graph are rebuilt); 100 more steps follow.  Every
+live case is then compared with the oracle run for 200 steps from the same
+seeded input: FP64 populations within 1e-11 relative, FP32 density within
+1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CASES = (14, 49, 12, 39, 58, 48, 6, 5, 54)   # indices into workloads.batch64()
+DIVERGING = dict(nx=20, ny=20, nz=24, tau=0.55, G=-6.0, rho_l=2.6, rho_v=0.04)
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_11792_amd import lbm as mod
+
+    return mod
+
+
+def _spec(c, rho_l, rho_v):
+    return dict(R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength, rho_l=rho_l, rho_v=rho_v,
+                noise_amp=1e-4, seed=c.seed)
+
+
+@pytest.fixture(scope="module")
+def reference(oracle_mod):
+    """Cases, their densities (the oracle's own coexistence runs) and the
+    oracle's populations after 200 steps."""
+    all_cases = workloads.batch64()
+    out = []
+    for i in CASES:
+        c = all_cases[i]
+        co = oracle_mod.coexistence(c.G, c.tau)
+        assert co.rho_l > co.rho_v > 0, i
+        spec = _spec(c, co.rho_l, co.rho_v)
+        f0 = oracle_mod.init_ligament(c.nx, c.ny, c.nz, **spec)
+        f = oracle_mod.run(f0, 200, c.tau, c.G)
+        assert oracle_mod.diag(f)["nonfinite"] == 0, i
+        out.append((c, spec, f))
+    return out
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+@pytest.mark.parametrize("storage,zchunk", [("f32", 6), ("f32", 8), ("f64", 8)])
+def test_batch_matches_oracle_across_graphs_and_compaction(lbm, reference, storage, zchunk):
+    import torch
+
+    d = DIVERGING
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage=storage) for c, _, _ in reference]
+    params.append(lbm.make_params(d["nx"], d["ny"], d["nz"], d["tau"], d["G"], storage=storage))
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, **spec) for c, spec, _ in reference]
+    specs.append(lbm.make_ligament(d["nx"], d["ny"], d["nz"], R0=4.0, amp_rel=0.1, wavelength=24.0,
+                                   rho_l=d["rho_l"], rho_v=d["rho_v"]))
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(params, stream=stream)
+    b.set_launch(0, 512, zchunk)
+    b.set_graph_chunk(20)
+    b.init(specs)
+    b.step(100)
+    diag = b.diagnostics()
+    assert diag[-1]["nonfinite"] > 0
+    assert all(x["nonfinite"] == 0 for x in diag[:-1])
+    b.step(100)
+    worst = 0.0
+    for i, (c, _, ref) in enumerate(reference):
+        if storage == "f64":
+            got = b.fields(i, rho=False, pop=True)["pop"].cpu().numpy()
+            err = _relerr(got, ref)
+            assert err < 1e-11, (i, err)
+        else:
+            got = b.fields(i)["rho"].cpu().numpy()
+            err = _relerr(got, ref.sum(axis=0))
+            assert err < 1e-5, (i, err)
+        worst = max(worst, err)
+    print(f"{storage} z chunk {zchunk}: worst error over {len(reference)} cases {worst:.2e}")
+    assert b.diagnostics()[-1]["nonfinite"] > 0  # the frozen case stays frozen
+    b.close()

@@ -193,10 +193,12 @@ def test_autotune_keeps_state_and_caches(lbm, tmp_path):
     try:
         lat = lbm.Lattice(40, 36, 48, 0.9, -5.5, storage="f32")
         lat.init_ligament(R0=8.0, amp_rel=0.1, wavelength=48.0, rho_l=2.3, rho_v=0.1, noise_amp=1e-3, seed=3)
+        lat.step(3)
         before = lat.populations().cpu().numpy()
         (tx, ty, zc), mlups = lat.autotune(2)
         assert (tx, ty) in lbm.lbm_list_tiles() and zc >= 1 and mlups > 0
         assert np.array_equal(lat.populations().cpu().numpy(), before)
+        assert lat.step_count == 3
         assert lat.get_launch() == (tx, ty, zc)
         cache = json.load(open(tmp_path / "tune.json"))
         assert any(v == [tx, ty, zc] for v in cache.values())
@@ -204,6 +206,110 @@ def test_autotune_keeps_state_and_caches(lbm, tmp_path):
         assert again.get_launch() == (tx, ty, zc)
     finally:
         del os.environ["LBM_TUNE_CACHE"]
+
+
+def _loop_ms(lbm, lat, steps=200, reps=3):
+    """Best of `reps` timings of `steps` steps of the ordinary step loop."""
+    import torch
+
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
+    return best
+
+
+def test_autotuned_launch_is_not_slower_in_the_step_loop(lbm):
+    """The autotuner times candidates in the alternating step loop, so its
+    pick must be at least as fast there as the default launch (it is one of
+    the candidates); 3% allows for timing noise.  64 x 64 x 144 FP32 is the
+    grid where a tuner that repeated one launch on a fixed state picked a
+    launch 15% slower in the real loop."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    lat = lbm.Lattice(64, 64, 144, 1.0, -5.5, storage="f32", stream=stream)
+    lat.init_ligament(R0=16.0, amp_rel=0.1, wavelength=144.0, rho_l=2.3068, rho_v=0.1041)
+    default = lat.get_launch()
+    (tx, ty, zc), _ = lat.autotune(20)
+    t_tuned = _loop_ms(lbm, lat)
+    lat.set_launch(*default)
+    t_default = _loop_ms(lbm, lat)
+    lat.set_launch(tx, ty, zc)
+    t_tuned = min(t_tuned, _loop_ms(lbm, lat))
+    print(f"default {default}: {t_default:.4f} ms, tuned {(tx, ty, zc)}: {t_tuned:.4f} ms")
+    assert t_tuned <= 1.03 * t_default
+
+
+def test_batch_autotune_keeps_state_and_is_not_slower(lbm):
+    import torch
+
+    cases = workloads.batch64(seed=11, count=6)
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
+                               rho_l=2.3, rho_v=0.1, seed=c.seed) for c in cases]
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(params, stream=stream)
+    b.init(specs)
+    b.step(3)
+    before = [b.fields(i, rho=False, pop=True)["pop"].cpu().numpy() for i in range(len(cases))]
+    default = (0, 512, 8)
+
+    def loop_ms(steps=100):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    (tx, ty, zc), mlups = b.autotune(10)
+    assert mlups > 0
+    for i in range(len(cases)):
+        assert np.array_equal(b.fields(i, rho=False, pop=True)["pop"].cpu().numpy(), before[i]), i
+    t_tuned = min(loop_ms() for _ in range(3))
+    b.set_launch(*default)
+    t_default = min(loop_ms() for _ in range(3))
+    print(f"batch default {default}: {t_default:.4f} ms, tuned {(tx, ty, zc)}: {t_tuned:.4f} ms")
+    assert t_tuned <= 1.03 * t_default
+    b.close()
+
+
+def test_side_stream_lattice_dropped_mid_run(lbm):
+    """A lattice working on a side stream, closed while its steps are still
+    queued: its workspace must not be handed to a new tensor before those
+    steps have finished (the new tensor's values, and the steps' own result
+    in a second lattice on the same stream, stay intact)."""
+    import torch
+
+    spec = dict(R0=10.0, amp_rel=0.1, wavelength=64.0, rho_l=2.3, rho_v=0.1, noise_amp=1e-3, seed=5)
+    s = torch.cuda.Stream()
+    keep = lbm.Lattice(96, 96, 64, 0.9, -5.5, storage="f32", stream=s)
+    keep.init_ligament(**spec)
+    ref = lbm.Lattice(96, 96, 64, 0.9, -5.5, storage="f32")
+    ref.init_ligament(**spec)
+    ref.step(40)
+    want = ref.populations().cpu().numpy()
+    ref.close()
+    nbytes = None
+    for _ in range(3):
+        drop = lbm.Lattice(96, 96, 64, 0.9, -5.5, storage="f32", stream=s)
+        drop.init_ligament(**spec)
+        drop.step(40)            # queued on s, long enough to still run below
+        nbytes = drop.workspace.numel()
+        drop.close()
+        del drop
+        fresh = torch.full((nbytes // 4,), 7.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        assert bool((fresh == 7.0).all())
+        del fresh
+    keep.step(40)
+    assert np.array_equal(keep.populations().cpu().numpy(), want)
+    keep.close()
 
 
 def test_full_size_benchmark_grid_parity(lbm, oracle_mod):

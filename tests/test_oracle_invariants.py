@@ -204,3 +204,61 @@ def test_droplet_labelling(oracle_mod):
     assert lab[0, 0, 0] == lab[5, 0, 0] != 0
     assert lab[2, 2, 2] == lab[2, 2, 3]
     assert lab[0, 3, 3] != lab[1, 4, 4]
+
+
+def _flat_interface(oracle_mod, G, tau, steps, n=128):
+    """A 1 x 1 x n periodic slab with liquid on [n/4, 3n/4), started from the
+    oracle's coexistence densities and run for `steps` steps."""
+    co = oracle_mod.coexistence(G, tau)
+    z = np.arange(n, dtype=np.float64)
+    rho = co.rho_v + (co.rho_l - co.rho_v) * 0.5 * (np.tanh(2 * (z - (n / 4 - 0.5)) / 4)
+                                                   - np.tanh(2 * (z - (3 * n / 4 - 0.5)) / 4))
+    f = _rest_populations(oracle_mod, rho.reshape(n, 1, 1))
+    return oracle_mod.run(f, steps, tau, G)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.3])
+def test_reported_velocity_vanishes_at_a_static_interface(oracle_mod, tau):
+    """The velocity the oracle reports is u = (j + F/2)/rho (Eqs. 4-6 with
+    the standard Shan-Chen hydrodynamic velocity).  At a converged flat
+    interface nothing moves, so the reported velocity must vanish, while the
+    bare j/rho is of order 0.2 there (the pre-collision momentum lags the
+    force by half of its effect).
+
+    Measured: max|u| / max|j/rho| = 3.8e-5 (tau 0.8) and 5.7e-5 (tau 1.3),
+    unchanged between 60k and 240k steps -- the discrete steady state's
+    O(dx^2) residual, not round-off.  The weight c of F in (j + c F)/rho
+    that best cancels the flux is 1/2 to that accuracy; a dropped 1/2
+    (c = 0), the post-collision momentum (c = 1) or the shift itself
+    (c = tau) would leave velocities of 0.1-0.2."""
+    f = _flat_interface(oracle_mod, -5.5, tau, 60_000)
+    fl = oracle_mod.fields(f, -5.5)
+    j, F, rho, u = fl["j"][2, :, 0, 0], fl["F"][2, :, 0, 0], fl["rho"][:, 0, 0], fl["u"][2, :, 0, 0]
+    bare = np.abs(j / rho).max()
+    assert bare > 0.1
+    assert np.abs(u).max() < 1e-4 * bare
+    c_best = -np.dot(j, F) / np.dot(F, F)  # least-squares weight making j + c F vanish
+    assert abs(c_best - 0.5) < 1e-3
+    for c in (0.0, 1.0, tau):
+        assert np.abs((j + c * F) / rho).max() > 0.1 * bare
+
+
+def test_reported_velocity_is_the_mid_collision_momentum(oracle_mod):
+    """Under the velocity shift of Eq. (6) a BGK collision changes the
+    momentum by exactly F (sum_a c_a f*_a = j + omega (rho u' - j) = j + F),
+    so (j + F/2) is the mean of the momenta before and after the collision.
+    The post-collision momentum is read back from the next state of the
+    oracle's own step (f*_a(x) = f_a(x + c_a, t + 1)), independent of the
+    code that reports the velocity."""
+    rho = workloads.smooth_density((6, 7, 8), seed=11, mean=1.0, amp=0.8)
+    f = workloads.random_populations((6, 7, 8), seed=12, base=1.0, spread=0.2) * 19 \
+        * _rest_populations(oracle_mod, rho)
+    tau, G = 0.85, -5.5
+    fl = oracle_mod.fields(f, G)
+    g = oracle_mod.step(f, tau, G)
+    cx, cy, cz, _ = oracle_mod.lattice()
+    post = np.stack([np.roll(g[a], (-cz[a], -cy[a], -cx[a]), axis=(0, 1, 2)) for a in range(19)])
+    jstar = np.stack([np.tensordot(c, post, axes=(0, 0)) for c in (cx, cy, cz)])
+    assert np.abs(fl["F"]).max() > 1e-2
+    assert np.allclose(jstar, fl["j"] + fl["F"], rtol=0, atol=1e-14)
+    assert np.allclose(fl["u"] * fl["rho"], 0.5 * (fl["j"] + jstar), rtol=0, atol=1e-14)
