@@ -174,6 +174,23 @@ int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lb
                          int32_t *status);
 
 /*
+ * lbm_coexistence_many without any device allocation, for callers that
+ * cannot allocate device memory (serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors, bit for bit the same
+ * densities, for at most LBM_NOALLOC_MAX_RUNS runs (more: INVALID_ARG
+ * before any device work).  Its device memory is a fixed library-owned
+ * array of about 1.3 MB per GPU (run states, results, case table), held
+ * until the process ends; every call on one GPU reuses it, so calls that
+ * overlap on the same GPU (from several host threads) race and must be
+ * serialised by the caller.  Synchronous; works on the null stream of the
+ * current device.
+ */
+enum { LBM_NOALLOC_MAX_RUNS = 64 };
+int lbm_coexistence_many_noalloc(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt,
+                                 int32_t psi, double rho0, double *rho_l, double *rho_v,
+                                 int32_t *status);
+
+/*
  * Select the collision of a context: mrt = NULL for BGK (the default), else
  * the MRT rates above (copied).  The MRT kernels are compiled for the
  * run-time tiles (tile_x = 0); if the current launch uses a compile-time

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdint>
 #include <cmath>
 #include <cstddef>
@@ -758,8 +759,43 @@ int coexistence_impl(double G, double tau, const lbm_mrt *mrt_in, int32_t psi, d
     return LBM_OK;
 }
 
+// ---- the allocation-free variant of lbm_coexistence_many ----------------
+//
+// Its device memory is a file-scope array, one per GPU, held until the
+// process ends: run states (19 x 128 doubles each), results (4 doubles each)
+// and the case table, for at most LBM_NOALLOC_MAX_RUNS runs.  Host code
+// reaches it only through the address hipGetSymbolAddress gives on each
+// device (the array's name is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocStateBytes = sizeof(double) * Q * kCoexNodes * LBM_NOALLOC_MAX_RUNS;
+constexpr size_t kNoAllocOutBytes = sizeof(double) * 4 * LBM_NOALLOC_MAX_RUNS;
+constexpr size_t kNoAllocBytes = kNoAllocStateBytes + kNoAllocOutBytes + sizeof(CoexCase) * LBM_NOALLOC_MAX_RUNS;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current).
+hipError_t noalloc_scratch(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char *>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
 int coexistence_many_impl(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
-                          double rho0, double *rho_l, double *rho_v, int32_t *status) {
+                          double rho0, double *rho_l, double *rho_v, int32_t *status, bool noalloc) {
     if (m < 1) return fail(LBM_ERR_INVALID_ARG, "m must be >= 1");
     if (!G || !tau || !rho_l || !rho_v || !status) return fail(LBM_ERR_INVALID_ARG, "an array pointer is NULL");
     if (mrt) {
@@ -777,8 +813,20 @@ int coexistence_many_impl(int32_t m, const double *G, const double *tau, const l
         }
         runs.emplace_back(G[j], tau[j], rho0, mp);
     }
-    const hipError_t e = run_coexistence(runs);
-    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "lbm_coexistence_many: %s", hipGetErrorString(e));
+    hipError_t e = hipSuccess;
+    if (noalloc) {
+        char *base = nullptr;
+        e = noalloc_scratch(&base);
+        if (e == hipSuccess)
+            e = run_coexistence_in(runs, reinterpret_cast<double *>(base),
+                                   reinterpret_cast<double *>(base + kNoAllocStateBytes),
+                                   reinterpret_cast<CoexCase *>(base + kNoAllocStateBytes + kNoAllocOutBytes));
+    } else {
+        e = run_coexistence(runs);
+    }
+    if (e != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "%s: %s", noalloc ? "lbm_coexistence_many_noalloc" : "lbm_coexistence_many",
+                    hipGetErrorString(e));
     int first_bad = -1, nbad = 0;
     for (int32_t j = 0; j < m; ++j) {
         const CoexRun &r = runs[size_t(j)];
@@ -809,7 +857,15 @@ int lbm_coexistence_mrt(double G, double tau, const lbm_mrt *mrt, int32_t psi, d
 
 int lbm_coexistence_many(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt, int32_t psi,
                          double rho0, double *rho_l, double *rho_v, int32_t *status) {
-    return coexistence_many_impl(m, G, tau, mrt, psi, rho0, rho_l, rho_v, status);
+    return coexistence_many_impl(m, G, tau, mrt, psi, rho0, rho_l, rho_v, status, false);
+}
+
+int lbm_coexistence_many_noalloc(int32_t m, const double *G, const double *tau, const lbm_mrt *mrt,
+                                 int32_t psi, double rho0, double *rho_l, double *rho_v, int32_t *status) {
+    if (m > LBM_NOALLOC_MAX_RUNS)
+        return fail(LBM_ERR_INVALID_ARG, "lbm_coexistence_many_noalloc takes at most %d runs (got %d)",
+                    int(LBM_NOALLOC_MAX_RUNS), m);
+    return coexistence_many_impl(m, G, tau, mrt, psi, rho0, rho_l, rho_v, status, true);
 }
 
 int lbm_set_mrt(lbm_ctx *c, const lbm_mrt *mrt) {

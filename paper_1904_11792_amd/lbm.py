@@ -39,6 +39,7 @@ LBM_PSI_EXP = 0
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S, LBM_F16M, LBM_BF16M = 0, 1, 2, 3, 4, 5
 LBM_FIELD_RHO, LBM_FIELD_U, LBM_FIELD_FORCE, LBM_FIELD_POP = 1, 2, 4, 8
 LBM_DIAG_RING = 4096
+LBM_NOALLOC_MAX_RUNS = 64
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S,
            "f16m": LBM_F16M, "bf16m": LBM_BF16M}
@@ -109,6 +110,8 @@ _SIGS = {
     "lbm_coexistence_mrt": (ctypes.c_int, [_d, _d, _P(lbm_mrt), _i32, _d, _P(_d), _P(_d)]),
     "lbm_coexistence_many": (ctypes.c_int, [_i32, _P(_d), _P(_d), _P(lbm_mrt), _i32, _d, _P(_d), _P(_d),
                                             _P(_i32)]),
+    "lbm_coexistence_many_noalloc": (ctypes.c_int, [_i32, _P(_d), _P(_d), _P(lbm_mrt), _i32, _d, _P(_d),
+                                                    _P(_d), _P(_i32)]),
     "lbm_set_mrt": (ctypes.c_int, [_vp, _P(lbm_mrt)]),
     "lbm_init_ligament": (ctypes.c_int, [_vp, _P(lbm_ligament)]),
     "lbm_step": (ctypes.c_int, [_vp, _i64]),
@@ -203,6 +206,13 @@ def lbm_coexistence_many(G, tau, psi: int = LBM_PSI_EXP, rho0: float = 1.0, mrt:
     Returns (rho_l, rho_v, status) as numpy arrays; a diverged run has status
     LBM_ERR_DIVERGED and NaN densities (no exception for that)."""
     return _coexistence_many(_lib.lbm_coexistence_many, G, tau, psi, rho0, mrt)
+
+
+def lbm_coexistence_many_noalloc(G, tau, psi: int = LBM_PSI_EXP, rho0: float = 1.0,
+                                 mrt: dict | None = None):
+    """lbm_coexistence_many on the library's fixed device array (no device
+    allocation; at most LBM_NOALLOC_MAX_RUNS runs)."""
+    return _coexistence_many(_lib.lbm_coexistence_many_noalloc, G, tau, psi, rho0, mrt)
 
 
 def _coexistence_many(fn, G, tau, psi, rho0, mrt):
