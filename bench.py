@@ -339,7 +339,8 @@ def study_precision(args, lbm, workloads, stream):
     import torch
 
     base = workloads.LARGE_FP32
-    cases = [base, dataclasses.replace(base, name="large G=-6.0", G=-6.0)]
+    cases = [base, dataclasses.replace(base, name="large G=-6.0", G=-6.0),
+             dataclasses.replace(base, name="large tau=1.0", tau=1.0)]
     out = []
     for spec in cases:
         rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
@@ -374,7 +375,8 @@ def study_precision(args, lbm, workloads, stream):
 
 
 def study_shift(args, lbm, workloads, stream):
-    """Shifted FP16 storage: break-up time and mass drift against the FP64 run
+    """Shifted 16-bit storage (--storage f16s, bf16s, f16m or bf16m; default
+    f16m): break-up time and mass drift against the FP64 run
     for several shift densities rho_ref (vapour, 0, the mean of the two phases,
     1) on the large ligament (two noise seeds, G -6.0, tau 1.0) and the R = 32
     grid of the convergence series."""
@@ -387,7 +389,8 @@ def study_shift(args, lbm, workloads, stream):
     out = []
     for spec in cases:
         rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
-        runs = [("f64", None, "-")] + [("f16s", r, name) for name, r in
+        kind = args.storage if args.storage in ("f16s", "bf16s", "f16m", "bf16m") else "f16m"
+        runs = [("f64", None, "-")] + [(kind, r, name) for name, r in
                                       (("rho_v", rho_v), ("0", 0.0), ("mid", 0.5 * (rho_l + rho_v)), ("1", 1.0))]
         ref, rows = None, []
         for storage, rref, name in runs:
@@ -401,7 +404,7 @@ def study_shift(args, lbm, workloads, stream):
             print(f"# {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
         out.append({"case": spec.name, "G": spec.G, "tau": spec.tau, "rho_l": rho_l, "rho_v": rho_v,
                     "rows": rows})
-    print(json.dumps({"study": "fp16_shift_density", "cases": out}))
+    print(json.dumps({"study": "shift_density", "storage": kind, "cases": out}))
 
 
 def study_convergence(args, lbm, workloads, stream):

@@ -323,6 +323,15 @@ int lbm_droplets(lbm_ctx *ctx, double rho_mid, lbm_droplet *out, int32_t max_out
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 
 /*
+ * Set the step counter (>= 0), e.g. when resuming from a checkpoint taken
+ * with lbm_get_fields / lbm_get_step: the stochastic rounding of the F16M and
+ * BF16M kinds draws its random numbers from (step, node), so a resumed run
+ * repeats the uninterrupted one bit for bit only at the same step number.
+ * The other kinds do not use it.
+ */
+int lbm_set_step(lbm_ctx *ctx, int64_t step);
+
+/*
  * Launch shape of the fused step kernel: an x-y tile of tile_x * tile_y
  * nodes (one thread each) marching zchunk planes along z.  Supported tiles:
  * see lbm_list_tiles.  tile_x = 0 selects a tile shaped at run time for the

@@ -691,6 +691,15 @@ hipError_t launch_diag(const LatticeRef &L, int axis, DiagPartial *partials,
     return hipGetLastError();
 }
 
+__global__ void k_counter(uint32_t *p, uint32_t v, int add) {
+    if (threadIdx.x == 0) *p = add ? *p + v : v;
+}
+
+hipError_t launch_counter(uint32_t *p, uint32_t v, bool add, hipStream_t s) {
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, p, v, add ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long *p, size_t count, unsigned long long v, hipStream_t s) {
     int64_t nbl = int64_t((count + kBlock - 1) / kBlock);
     const int nb = int(nbl < 1 ? 1 : (nbl > 65536 ? 65536 : nbl));

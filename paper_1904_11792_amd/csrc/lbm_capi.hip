@@ -76,7 +76,7 @@ struct Layout {
     int64_t S;       // population stride (elements)
     int R, P;        // record and plane strides (elements)
     int rec_shift;   // rows per record = 2^rec_shift
-    size_t lat_bytes, off_lat1, off_part, off_slices, off_latest, off_ring, total;
+    size_t lat_bytes, off_lat1, off_part, off_slices, off_latest, off_ring, off_counter, total;
     int nparts, nslices;
 };
 
@@ -129,7 +129,8 @@ Layout layout_of(const lbm_params *p) {
     L.off_slices = L.off_part + align_up(sizeof(DiagPartial) * L.nparts, 256);
     L.off_latest = L.off_slices + align_up(sizeof(unsigned long long) * L.nslices, 256);
     L.off_ring = L.off_latest + align_up(sizeof(DiagRecord), 256);
-    L.total = L.off_ring + align_up(sizeof(DiagRecord) * LBM_DIAG_RING, 256);
+    L.off_counter = L.off_ring + align_up(sizeof(DiagRecord) * LBM_DIAG_RING, 256);
+    L.total = L.off_counter + 256;
     return L;
 }
 
@@ -307,6 +308,11 @@ struct lbm_ctx {
     hipGraphExec_t gexec;
     lbm_launch graph_launch;
     MrtParams mrt;  // collision operator (mrt.on = 0: BGK)
+    // Device step counter read by the step kernels (the key of the
+    // stochastic rounding): a launch's step is *counter + step_add.  dstep is
+    // the value the counter holds when the next enqueued launch runs.
+    uint32_t *counter;
+    uint32_t dstep;
 };
 
 namespace {
@@ -360,6 +366,8 @@ StepArgs step_args(const lbm_ctx *c, const lbm_launch &l, int src) {
     A.rho0 = c->p.rho0;
     A.rho_ref = is_shifted(c->p.storage) ? c->p.rho_ref : 0.0;
     A.mrt = c->mrt;
+    A.step_base = c->counter;
+    A.step_add = uint32_t(c->step) - c->dstep;
     return A;
 }
 
@@ -382,16 +390,19 @@ void release_graph(lbm_ctx *c) {
     }
 }
 
-// Capture graph_chunk steps starting from lattice 0.
+// Capture graph_chunk steps starting from lattice 0, the s-th at step
+// *counter + s, then the counter's advance by graph_chunk.
 hipError_t build_graph(lbm_ctx *c) {
     release_graph(c);
     hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     for (int s = 0; s < c->graph_chunk; ++s) {
-        const StepArgs A = step_args(c, c->launch, s & 1);
+        StepArgs A = step_args(c, c->launch, s & 1);
+        A.step_add = uint32_t(s);
         e = launch_step(c->tile_index, c->p.storage, A, c->stream);
         if (e != hipSuccess) break;
     }
+    if (e == hipSuccess) e = launch_counter(c->counter, uint32_t(c->graph_chunk), true, c->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     if (e == hipSuccess) e = e2;
@@ -499,11 +510,14 @@ int lbm_create(const lbm_params *p, void *d_workspace, size_t ws_bytes, void *hi
     c->graph_chunk = 0;
     c->gexec = nullptr;
     c->mrt = MrtParams{};
+    c->counter = reinterpret_cast<uint32_t *>(c->ws + lay.off_counter);
+    c->dstep = 0;
     lbm_launch l;
     if (!cache_lookup(tune_key(p), &l) || check_launch(&l, p->storage) != LBM_OK) l = default_launch(p);
     c->launch = l;
     c->tile_index = find_tile(l.tile_x, l.tile_y);
     hipError_t e = launch_fill_u64(c->slices, lay.nslices, 0ull, c->stream);
+    if (e == hipSuccess) e = launch_counter(c->counter, 0u, false, c->stream);
     if (e != hipSuccess) {
         delete c;
         return fail(LBM_ERR_DEVICE, "lbm_create: %s", hipGetErrorString(e));
@@ -943,9 +957,14 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
         }
         if (e == hipSuccess && (!c->gexec || memcmp(&c->graph_launch, &c->launch, sizeof(lbm_launch)) != 0))
             e = build_graph(c);
+        if (e == hipSuccess && c->dstep != uint32_t(c->step)) {  // the graph counts from *counter
+            e = launch_counter(c->counter, uint32_t(c->step), false, c->stream);
+            c->dstep = uint32_t(c->step);
+        }
         while (e == hipSuccess && left >= c->graph_chunk) {
             e = hipGraphLaunch(c->gexec, c->stream);
             c->step += c->graph_chunk;
+            c->dstep += uint32_t(c->graph_chunk);
             left -= c->graph_chunk;
         }
     }
@@ -1109,6 +1128,14 @@ int lbm_read_diag_history(lbm_ctx *c, lbm_diag *out, int32_t max, int32_t *count
 int lbm_get_step(const lbm_ctx *c, int64_t *step) {
     if (!c || !step) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
     *step = c->step;
+    return LBM_OK;
+}
+
+int lbm_set_step(lbm_ctx *c, int64_t step) {
+    int st = check_ctx(c);
+    if (st != LBM_OK) return st;
+    if (step < 0) return fail(LBM_ERR_INVALID_ARG, "step must be >= 0");
+    c->step = step;
     return LBM_OK;
 }
 
@@ -1302,6 +1329,8 @@ struct lbm_batch {
     hipEvent_t ev_frozen;
     bool frozen_pending;
     std::vector<uint8_t> dropped;
+    uint32_t *counter;  // device step counter, as in lbm_ctx
+    uint32_t dstep;
 };
 
 namespace {
@@ -1320,7 +1349,7 @@ int64_t items_for(const lbm_params &p, int tx, int ty, int zc) {
 }
 
 struct BatchLayout {
-    size_t off_cases, off_items, off_frozen, off_records, off_partials, off_slices, off_lat, total;
+    size_t off_cases, off_items, off_frozen, off_records, off_partials, off_slices, off_counter, off_lat, total;
     size_t item_capacity;
     int max_parts, max_slices;
     std::vector<Layout> lay;
@@ -1337,6 +1366,8 @@ BatchLayout batch_layout(int n, const lbm_params *p) {
         tile_shape(t, &tx, &ty);
         size_t cnt = 0;
         for (int i = 0; i < n; ++i) cnt += size_t(items_for(p[i], tx, ty, kBatchMinZchunk));
+        // the launch list pads each XCD's share to the longest one (batch_upload)
+        cnt = 8 * cnt + 8;
         if (cnt > B.item_capacity) B.item_capacity = cnt;
     }
     for (int i = 0; i < n; ++i) {
@@ -1357,6 +1388,8 @@ BatchLayout batch_layout(int n, const lbm_params *p) {
     off += align_up(sizeof(DiagPartial) * B.max_parts, 256);
     B.off_slices = off;
     off += align_up(sizeof(unsigned long long) * B.max_slices, 256);
+    B.off_counter = off;
+    off += 256;
     B.off_lat = off;
     for (int i = 0; i < n; ++i) {
         B.lat_off.push_back(off);
@@ -1415,9 +1448,26 @@ LatticeRef batch_ref(const lbm_batch *b, int i, int which) {
 }
 
 // Rebuild the device case table and item list for the current launch shape.
+//
+// Work items are (case, tile, z chunk) triples of the cases still running.
+// The hardware hands workgroup b to XCD b mod 8, and each XCD runs its
+// workgroups in launch order, so the list is built per XCD and interleaved:
+//  - the items, in (case, chunk, tile) order, are cut into 8 runs of equal
+//    estimated cost, one per XCD: neighbouring tiles and chunks of a case,
+//    whose ring and boundary planes overlap, meet in one L2, and every XCD
+//    has the same amount of work;
+//  - within a run the items go longest first, so that each XCD ends on its
+//    shortest items and the step's tail is short;
+//  - runs shorter than the longest are padded with empty items (case -1).
+// Cost of an item: (planes + 2) x (tile nodes + ring nodes), the two extra
+// planes being the chunk's boundary gathers.
 hipError_t batch_upload(lbm_batch *b) {
     std::vector<BatchCase> cases(b->n);
-    std::vector<int4> items;
+    struct Item {
+        int4 it;
+        double cost;
+    };
+    std::vector<Item> all;
     const lbm_launch &l = b->launch;
     for (int i = 0; i < b->n; ++i) {
         StepArgs A;
@@ -1444,15 +1494,38 @@ hipError_t batch_upload(lbm_batch *b) {
         cases[i].lat[0] = case_lat(b, i, 0);
         cases[i].lat[1] = case_lat(b, i, 1);
         if (b->dropped[i]) continue;  // frozen: its workgroups would only exit
-        // chunk-major, tile fastest: consecutive items are x-y neighbours of one case
-        for (int c = 0; c < A.nchunks; ++c)
-            for (int t = 0; t < A.tiles_x * A.tiles_y; ++t) items.push_back(make_int4(i, t, c, 0));
+        const double area = double(A.tile_w) * A.tile_h + 2.0 * (A.tile_w + 2) + 2.0 * A.tile_h;
+        for (int c = 0; c < A.nchunks; ++c) {
+            const int planes = std::min(A.zchunk, A.nz - c * A.zchunk);
+            for (int t = 0; t < A.tiles_x * A.tiles_y; ++t)
+                all.push_back(Item{make_int4(i, t, c, 0), (planes + 2) * area});
+        }
     }
+    double total = 0;
+    for (const Item &it : all) total += it.cost;
+    constexpr int kXcd = 8;
+    std::vector<std::vector<Item>> run(kXcd);
+    double acc = 0;
+    for (const Item &it : all) {
+        int x = int(acc / total * kXcd);  // the run this item's cost midpoint falls in
+        acc += it.cost;
+        x = std::min(std::max(x, 0), kXcd - 1);
+        run[x].push_back(it);
+    }
+    size_t longest = 0;
+    for (auto &r : run) {
+        std::stable_sort(r.begin(), r.end(), [](const Item &p, const Item &q) { return p.cost > q.cost; });
+        longest = std::max(longest, r.size());
+    }
+    std::vector<int4> items;
+    items.reserve(kXcd * longest);
+    for (size_t j = 0; j < longest && !all.empty(); ++j)
+        for (int x = 0; x < kXcd; ++x) items.push_back(j < run[x].size() ? run[x][j].it : make_int4(-1, 0, 0, 0));
     if (items.size() > b->item_capacity) return hipErrorInvalidValue;  // zchunk below the sized minimum
     b->nitems = int(items.size());
     hipError_t e = hipMemcpyAsync(b->d_cases, cases.data(), sizeof(BatchCase) * b->n, hipMemcpyHostToDevice,
                                   b->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !items.empty())
         e = hipMemcpyAsync(b->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
                            b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // host vectors die here
@@ -1472,7 +1545,8 @@ hipError_t batch_plain(lbm_batch *b, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
         if (b->nitems > 0) {  // no items: every case is frozen
             hipError_t e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
-                                             b->d_frozen, b->parity, b->stream);
+                                             b->d_frozen, b->parity, b->counter, uint32_t(b->step) - b->dstep,
+                                             b->stream);
             if (e != hipSuccess) return e;
         }
         b->parity ^= 1;
@@ -1494,7 +1568,8 @@ hipError_t batch_build_graph(lbm_batch *b) {
     if (e != hipSuccess) return e;
     for (int s = 0; s < b->graph_chunk && e == hipSuccess; ++s)
         e = launch_step_batch(b->tile_index, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
-                              s & 1, b->stream);
+                              s & 1, b->counter, uint32_t(s), b->stream);
+    if (e == hipSuccess) e = launch_counter(b->counter, uint32_t(b->graph_chunk), true, b->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (e == hipSuccess) e = e2;
@@ -1581,6 +1656,8 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
     b->d_records = reinterpret_cast<DiagRecord *>(b->ws + B.off_records);
     b->d_partials = reinterpret_cast<DiagPartial *>(b->ws + B.off_partials);
     b->d_slices = reinterpret_cast<unsigned long long *>(b->ws + B.off_slices);
+    b->counter = reinterpret_cast<uint32_t *>(b->ws + B.off_counter);
+    b->dstep = 0;
     b->item_capacity = B.item_capacity;
     b->parity = 0;
     b->step = 0;
@@ -1600,6 +1677,7 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
                                  hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_frozen, hipEventDisableTiming);
     if (e == hipSuccess) e = launch_fill_u64(b->d_slices, B.max_slices, 0ull, b->stream);
+    if (e == hipSuccess) e = launch_counter(b->counter, 0u, false, b->stream);
     if (e == hipSuccess) e = batch_upload(b);
     if (e != hipSuccess) {
         if (b->ev_frozen) (void)hipEventDestroy(b->ev_frozen);
@@ -1716,9 +1794,14 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
             }
             if (e == hipSuccess && (!b->gexec || memcmp(&b->graph_launch, &b->launch, sizeof(lbm_launch)) != 0))
                 e = batch_build_graph(b);
+            if (e == hipSuccess && b->dstep != uint32_t(b->step)) {
+                e = launch_counter(b->counter, uint32_t(b->step), false, b->stream);
+                b->dstep = uint32_t(b->step);
+            }
             while (e == hipSuccess && r >= b->graph_chunk) {
                 e = hipGraphLaunch(b->gexec, b->stream);
                 b->step += b->graph_chunk;
+                b->dstep += uint32_t(b->graph_chunk);
                 r -= b->graph_chunk;
             }
         }
@@ -1840,7 +1923,8 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
                 if (b->nitems > 0)
                     for (int q = 0; q < 2 && r == hipSuccess; ++q)
                         r = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
-                                              b->d_frozen, b->parity ^ q, b->stream);
+                                              b->d_frozen, b->parity ^ q, b->counter,
+                                              uint32_t(b->step) - b->dstep, b->stream);
                 return r;
             };
             e = two_steps();  // warm-up

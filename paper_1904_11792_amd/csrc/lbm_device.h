@@ -32,10 +32,11 @@ constexpr int kNumStorage = 6;
 // Shifted kinds hold f_a - w_a rho_ref, rounded to nearest even.
 //
 // kMassRest (F16M, BF16M): the 18 moving populations are stored shifted in
-// 16 bits and the rest population, shifted, in FP32; the arithmetic works on
-// the shifted values h_a = f_a - w_a rho_ref themselves (decode returns h_a),
-// and the collision sets the rest population from the node's mass minus the
-// moving populations as they are stored (collide_shifted).  A node's stored
+// 16 bits (stochastically rounded) and the rest population, shifted, in FP32;
+// the arithmetic works on the shifted values h_a = f_a - w_a rho_ref
+// themselves (decode returns h_a), and the collision sets the rest
+// population from the node's mass minus the moving populations as they are
+// stored (collide_shifted).  A node's stored
 // mass then equals the mass the collision conserves to FP32 rounding, where
 // with every population in 16 bits it moved by up to 19 half-precision
 // roundings per step, one-signed wherever the values repeat from step to step.
@@ -72,6 +73,7 @@ template <> struct Storage<kF16M> {
     using T = _Float16;
     using C = float;
     static constexpr bool kShifted = true, kMassRest = true;
+    static constexpr int kDropBits = 13;  // FP32 mantissa bits below the half's last bit
     __device__ static C decode(T v, C) { return static_cast<float>(v); }
     __device__ static T encode(C h, C) { return static_cast<_Float16>(h); }
 };
@@ -79,9 +81,56 @@ template <> struct Storage<kBF16M> {
     using T = __bf16;
     using C = float;
     static constexpr bool kShifted = true, kMassRest = true;
+    static constexpr int kDropBits = 16;  // FP32 mantissa bits below the bfloat16's last bit
     __device__ static C decode(T v, C) { return static_cast<float>(v); }
     __device__ static T encode(C h, C) { return static_cast<__bf16>(h); }
 };
+
+// Counter-based random bits for the stochastic rounding of the FP32-rest
+// kinds: the "lowbias32" integer hash (C. Wellons, "Prospecting for hash
+// functions", 2018), applied to the node index xor a per-step key.
+__host__ __device__ inline uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Stochastic rounding of the 18 moving populations h[1..18] (FP32) to the
+// 16-bit storage type, into out[1..18], returning their FP32 sum.  A value
+// is rounded up in magnitude with probability (distance to the lower
+// neighbour) / (spacing), so the rounding error has zero mean: increments
+// smaller than the 16-bit spacing survive on average instead of being
+// rounded away step after step (round-to-nearest holds a slowly changing
+// population at the same stored value, and a slowly growing flow with it).
+// Population a takes the 8 random bits at offset 4 ((a - 1) mod 6) of word
+// (a - 1) / 6 (overlapping windows, each uniform); they are added, with half a unit of the
+// byte, at the top of the FP32 mantissa bits the 16-bit type drops, and the
+// sum is truncated.  Below the half-precision normal range (|h| < 2^-14, a
+// spacing of 2^-24) F16M truncates toward zero.
+template <typename Tr>
+__device__ inline float round_moving_sr(const float (&h)[Q], typename Tr::T (&out)[Q], const uint32_t (&rnd)[3]) {
+    constexpr int D = Tr::kDropBits;
+    float sum = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+        const uint32_t byte = __builtin_amdgcn_ubfe(rnd[(a - 1) / 6], 4 * ((a - 1) % 6), 8);
+        const uint32_t bits = __float_as_uint(h[a]) + ((byte << (D - 8)) | (1u << (D - 9)));
+        float r;
+        if constexpr (D == 16) {  // bfloat16: the upper half of the FP32 pattern
+            const uint32_t t = bits & 0xFFFF0000u;
+            out[a] = __builtin_bit_cast(typename Tr::T, static_cast<uint16_t>(t >> 16));
+            r = __uint_as_float(t);
+        } else {  // half: truncating conversion of the perturbed value
+            out[a] = __builtin_amdgcn_cvt_pkrtz(__uint_as_float(bits), 0.0f)[0];
+            r = static_cast<float>(out[a]);
+        }
+        sum = (a == 1) ? r : sum + r;
+    }
+    return sum;
+}
 
 // Slots of 16-bit elements per node and population index -> slot: with an
 // FP32 rest population the rest takes two slots (0 and 1) and population
@@ -177,9 +226,10 @@ __device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
 // magnitudes span more than 24 bits, then the FP32 rest); j = sum c_a h_a
 // (sum_a c_a w_a = 0); the equilibrium minus the shift is
 // w_a (m + rho (4.5 (c.u')^2 - 1.5 u'^2)) +- 3 w_a rho c.u'.  The moving
-// populations leave rounded to the storage type (`out`, slots 1..18); the
-// rest population becomes m minus their exact FP32 sum, so the node's stored
-// mass is m to within one FP32 rounding.
+// populations leave stochastically rounded to the storage type (`out`,
+// slots 1..18, round_moving_sr with the node's random words `rnd`); the rest
+// population becomes m minus their exact FP32 sum, so the node's stored mass
+// is m to within one FP32 rounding.
 template <typename Tr>
 __device__ inline float shifted_excess(const float (&h)[Q]) {
     float s = h[1];
@@ -190,7 +240,7 @@ __device__ inline float shifted_excess(const float (&h)[Q]) {
 
 template <typename Tr>
 __device__ inline void collide_shifted(float (&h)[Q], typename Tr::T (&out)[Q], float Fx, float Fy, float Fz,
-                                       float tau, float omega, float rho_ref) {
+                                       float tau, float omega, float rho_ref, const uint32_t (&rnd)[3]) {
     using C = float;
     const C m = shifted_excess<Tr>(h);
     const C rho = rho_ref + m;
@@ -221,14 +271,7 @@ __device__ inline void collide_shifted(float (&h)[Q], typename Tr::T (&out)[Q], 
     LBM_SPAIR(15, uy + uz, 1.0 / 36.0)
     LBM_SPAIR(17, uy - uz, 1.0 / 36.0)
 #undef LBM_SPAIR
-    C moving = 0;
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-        out[a] = Tr::encode(h[a], C(0));
-        const C r = static_cast<C>(out[a]);
-        moving = (a == 1) ? r : moving + r;
-    }
-    h[0] = m - moving;
+    h[0] = m - round_moving_sr<Tr>(h, out, rnd);
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,12 @@ struct StepArgs {
     int row_stride, plane_stride, rec_shift;
     double tau, G, rho0, rho_ref;
     MrtParams mrt;
+    // Step number of this launch: *step_base + step_add (mod 2^32).  It keys
+    // the counter-based random numbers of the stochastic rounding
+    // (kStochastic storage kinds); a captured graph replays fixed step_add
+    // values over a base the host advances on the device.
+    const uint32_t *step_base;
+    uint32_t step_add;
 };
 
 // One case of a batch: its step arguments (src/dst unset) and both lattices.
@@ -125,7 +131,7 @@ bool tile_has_storage(int tile_index, int storage);
 int launch_slots(int tile_index, int storage);
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
                              const int4 *items, int nitems, const int32_t *frozen, int parity,
-                             hipStream_t s);
+                             const uint32_t *step_base, uint32_t step_add, hipStream_t s);
 
 // lbm_aux.hip
 hipError_t launch_init_ligament(const LatticeRef &L, const LigamentArgs &g, hipStream_t s);
@@ -149,6 +155,8 @@ hipError_t launch_droplets_label(const LatticeRef &L, double rho_mid, const Drop
 // Writes one entry per component (at most cap) into out, in no particular order.
 hipError_t launch_droplets_table(const DropletScratch &w, int n, DropletEntry *out, int cap, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// One-thread update of a device step counter: *p = v, or *p += v when add.
+hipError_t launch_counter(uint32_t *p, uint32_t v, bool add, hipStream_t s);
 // Flat-interface coexistence runs, one workgroup each: `chunk` steps on the
 // 1 x 1 x n slab held in each case's `state` ([19][n] doubles); init != 0
 // first writes the start profile (liquid hi on [n/4, 3n/4), vapour lo

@@ -39,8 +39,9 @@ __host__ __device__ constexpr int dyn_window(int threads) { return threads == 51
 __host__ __device__ constexpr int dyn_width_cap(int threads) { return threads == 512 ? 128 : 256; }
 
 // PRIO: gathers issued at raised wave priority (single-lattice launches).
+// tstep: the step number (keys the stochastic rounding of the FP32-rest kinds).
 template <int ST, int TXS, int TYS, bool MRT, bool PRIO>
-__device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk) {
+__device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk, uint32_t tstep) {
     using Tr = Storage<ST>;
     using T = typename Tr::T;
     using C = typename Tr::C;
@@ -71,6 +72,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 #pragma unroll
     for (int a = 0; a < Q; ++a) shift[a] = Tr::kShifted ? C(weight(a) * A.rho_ref) : C(0);
     const C rho_ref = C(A.rho_ref);
+    // per-step keys of the node hashes (wave-uniform)
+    uint32_t skey[3] = {0u, 0u, 0u};
+    if constexpr (MR) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) skey[k] = hash32(3u * tstep + uint32_t(k) + 0x9E3779B9u);
+    }
     // density of a node from its (decoded) populations; with kMassRest the
     // values are h_a and the density is rho_ref + sum h_a
     auto node_density = [&](const C(&f)[Q]) -> C {
@@ -102,10 +109,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // (records of rowst 16-bit slots are rowst / 2 floats apart)
     const int YR = MR ? row_offset(gy, rowst / 2, rsh, nx) : 0;
 
-    // Ring node handled by this thread (t < RING), in tile coordinates [-1, TX] x [-1, TY].
-    const bool ring = t < RING;
+    // A tile that spans whole rows (TX == nx) finds the psi of its left and
+    // right ring columns among its own nodes (periodic in x), and one that
+    // spans the whole cross-section its top and bottom rows as well: those
+    // ring nodes are not gathered; the owning threads copy their psi into
+    // the ghost cells of the window instead (same values, fewer gathers).
+    const bool full_w = TX == nx, full_h = full_w && TY == ny;
+    // Ring node handled by this thread (t < RING), in tile coordinates [-1, TX] x [-1, TY]:
+    // the whole ring; the top and bottom rows without corners when full_w;
+    // none when full_h.
+    const int RING_N = full_h ? 0 : (full_w ? 2 * TX : RING);
+    const bool ring = t < RING_N;
     int rx = 0, ry = 0;
-    if (t < PX) {
+    if (full_w) {
+        rx = t < TX ? t : t - TX;
+        ry = t < TX ? -1 : TY;
+    } else if (t < PX) {
         rx = t - 1;
         ry = -1;
     } else if (t < 2 * PX) {
@@ -154,16 +173,29 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 #pragma unroll
         for (int a = 0; a < Q; ++a) f[a] = (MR && a == 0) ? C(rest) : Tr::decode(raw[a], shift[a]);
     };
+    // psi of the node at window cell (yy, xx) into slot s, and into the ghost
+    // cells that hold the same node when the tile spans whole rows or the
+    // whole cross-section.
+    auto put_row = [&](int s, int yy, int xx, C v) {
+        W(s, yy, xx) = v;
+        if (full_w && xx == TX) W(s, yy, 0) = v;
+        if (full_w && xx == 1) W(s, yy, TX + 1) = v;
+    };
+    auto put = [&](int s, int yy, int xx, C v) {
+        put_row(s, yy, xx, v);
+        if (full_h && yy == TY) put_row(s, 0, xx, v);
+        if (full_h && yy == 1) put_row(s, TY + 1, xx, v);
+    };
     // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
     auto load_plane = [&](int zc, int s, C(&f)[Q]) {
         if (inside) {
             gather(zc, X, Y, YR, f);
-            W(s, ly + 1, lx + 1) = pseudo_potential(node_density(f), rho0, inv_rho0);
+            put(s, ly + 1, lx + 1, pseudo_potential(node_density(f), rho0, inv_rho0));
         }
         if (ring) {
             C g[Q];
             gather(zc, RX, RY, RYR, g);
-            W(s, ry + 1, rx + 1) = pseudo_potential(node_density(g), rho0, inv_rho0);
+            put(s, ry + 1, rx + 1, pseudo_potential(node_density(g), rho0, inv_rho0));
         }
     };
 
@@ -191,7 +223,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         int o = Y[1] + X[1];
         if constexpr (MR) {
             T out[Q];
-            collide_shifted<Tr>(f, out, Fx, Fy, Fz, tau, omega, rho_ref);
+            // random words of this node and step (node index as in the canonical layout)
+            const uint32_t node = (uint32_t(zc) * uint32_t(ny) + uint32_t(gy)) * uint32_t(nx) + uint32_t(gx);
+            const uint32_t rnd[3] = {hash32(node ^ skey[0]), hash32(node ^ skey[1]), hash32(node ^ skey[2])};
+            collide_shifted<Tr>(f, out, Fx, Fy, Fz, tau, omega, rho_ref, rnd);
             int orr = YR + X[1];
             asm volatile("" : "+v"(o), "+v"(orr));  // as in gather: form each store address here
             __builtin_nontemporal_store(f[0], &reinterpret_cast<float *>(zb)[orr]);
@@ -227,7 +262,9 @@ __device__ __forceinline__ void step_grid(const StepArgs &A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
-    step_tile<ST, TX, TY, MRT, true>(A, tile % A.tiles_x, tile / A.tiles_x, chunk);
+    uint32_t tstep = 0;
+    if constexpr (Storage<ST>::kMassRest) tstep = *A.step_base + A.step_add;
+    step_tile<ST, TX, TY, MRT, true>(A, tile % A.tiles_x, tile / A.tiles_x, chunk, tstep);
 }
 
 template <int ST, int TX, int TY>
@@ -242,20 +279,24 @@ __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_mrt(StepArgs A) {
 
 // Batched form: one launch covers every case's work items.  Items are
 // (case, tile, chunk) triples; case parameters and lattice pointers come from
-// a device table; frozen cases are skipped.
+// a device table; frozen cases and padding items (case -1) are skipped.  The
+// host orders the list by XCD (workgroup b runs on XCD b mod 8), so the
+// workgroup index is used as is.
 template <int ST, int TX, int TY>
 __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_batch(const BatchCase *__restrict__ cases,
                                                        const int4 *__restrict__ items,
                                                        const int32_t *__restrict__ frozen,
-                                                       int parity) {
-    const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int4 it = items[lb];
-    if (frozen[it.x]) return;
+                                                       int parity, const uint32_t *step_base,
+                                                       uint32_t step_add) {
+    const int4 it = items[blockIdx.x];
+    if (it.x < 0 || frozen[it.x]) return;
     const BatchCase &bc = cases[it.x];
     StepArgs A = bc.args;
     A.src = bc.lat[parity];
     A.dst = bc.lat[parity ^ 1];
-    step_tile<ST, TX, TY, false, false>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z);
+    uint32_t tstep = 0;
+    if constexpr (Storage<ST>::kMassRest) tstep = *step_base + step_add;
+    step_tile<ST, TX, TY, false, false>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z, tstep);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,10 +394,10 @@ hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream
 
 hipError_t launch_step_batch(int tile_index, int storage, const BatchCase *cases,
                              const int4 *items, int nitems, const int32_t *frozen, int parity,
-                             hipStream_t s) {
+                             const uint32_t *step_base, uint32_t step_add, hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
     if (!e.batch_fn[storage]) return hipErrorInvalidDeviceFunction;
-    void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity};
+    void *kargs[] = {(void *)&cases, (void *)&items, (void *)&frozen, &parity, (void *)&step_base, &step_add};
     const int threads = e.tx ? e.tx * e.ty : e.ty;
     return hipLaunchKernel(e.batch_fn[storage], dim3(nitems), dim3(threads), kargs, 0, s);
 }

@@ -122,6 +122,7 @@ _SIGS = {
     "lbm_record_diag": (ctypes.c_int, [_vp]),
     "lbm_read_diag_history": (ctypes.c_int, [_vp, _P(lbm_diag), _i32, _P(_i32)]),
     "lbm_get_step": (ctypes.c_int, [_vp, _P(_i64)]),
+    "lbm_set_step": (ctypes.c_int, [_vp, _i64]),
     "lbm_droplets": (ctypes.c_int, [_vp, _d, _P(lbm_droplet), _i32, _P(_i64)]),
     "lbm_set_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_get_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
@@ -294,6 +295,10 @@ def lbm_get_step(ctx) -> int:
     return s.value
 
 
+def lbm_set_step(ctx, step: int) -> None:
+    _check(_lib.lbm_set_step(ctx, int(step)))
+
+
 def lbm_set_launch(ctx, tile_x: int, tile_y: int, zchunk: int) -> None:
     _check(_lib.lbm_set_launch(ctx, ctypes.byref(lbm_launch(tile_x, tile_y, zchunk))))
 
@@ -410,6 +415,9 @@ class Lattice:
     @property
     def step_count(self) -> int:
         return lbm_get_step(self.ctx)
+
+    def set_step(self, step: int) -> None:
+        lbm_set_step(self.ctx, step)
 
     def fields(self, rho=True, u=False, force=False, pop=False) -> dict:
         """FP64 device tensors: rho (nz,ny,nx), u/force (3,nz,ny,nx), pop (19,nz,ny,nx)."""

@@ -176,13 +176,18 @@ def test_coexistence_matches_oracle(lbm, oracle_mod):
         assert rv == pytest.approx(co.rho_v, rel=1e-8), (G, tau)
 
 
-def test_graph_replay_equals_plain_launches(lbm):
+@pytest.mark.parametrize("storage", ["f32", "f16m"])
+def test_graph_replay_equals_plain_launches(lbm, storage):
+    """Captured chunks of 10 steps against plain launches, bitwise, over
+    several replays with eager work between them; for f16m the graph's
+    launches take their step numbers (which key the stochastic rounding)
+    from the device counter the graph advances."""
     import torch
 
     spec = dict(R0=5.0, amp_rel=0.1, wavelength=32.0, rho_l=RHO_L, rho_v=RHO_V, noise_amp=1e-3, seed=3)
     s = torch.cuda.Stream()
-    a = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage="f32", stream=s)
-    b = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage="f32", stream=s)
+    a = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage=storage, rho_ref=RHO_V, stream=s)
+    b = lbm.Lattice(20, 20, 32, 0.9, -5.5, storage=storage, rho_ref=RHO_V, stream=s)
     a.init_ligament(**spec)
     b.init_ligament(**spec)
     b.set_graph_chunk(10)
@@ -192,6 +197,11 @@ def test_graph_replay_equals_plain_launches(lbm):
         pa = a.populations().cpu().numpy()
         pb = b.populations().cpu().numpy()
         assert np.array_equal(pa, pb), k
+    a.set_step(7)  # a new step number: both agree again after the resynchronised graph
+    b.set_step(7)
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
 
 
 def test_translation_equivariance_on_gpu(lbm):
@@ -301,17 +311,18 @@ def test_run_time_tiles_on_wide_grid(lbm, oracle_mod, storage, nx):
         lat.close()
 
 
-def test_batch_case_equals_single_run(lbm):
+@pytest.mark.parametrize("storage", ["f32", "f16m"])
+def test_batch_case_equals_single_run(lbm, storage):
     cases = workloads.batch64(seed=7, count=5)
-    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32") for c in cases]
+    params = [lbm.make_params(c.nx, c.ny, c.nz, c.tau, c.G, storage=storage, rho_ref=RHO_V) for c in cases]
     specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
                                rho_l=RHO_L, rho_v=RHO_V, seed=c.seed) for c in cases]
     b = lbm.Batch(params)
     b.init(specs)
     b.step(30)
     for i, c in enumerate(cases):
-        single = lbm.Lattice(c.nx, c.ny, c.nz, c.tau, c.G, storage="f32")
-        b_launch = (0, 512, 16)  # the batch's default: run-time shaped full-row tiles
+        single = lbm.Lattice(c.nx, c.ny, c.nz, c.tau, c.G, storage=storage, rho_ref=RHO_V)
+        b_launch = (0, 512, 16)  # a run-time shaped full-row tile, another z chunk than the batch's
         single.set_launch(*b_launch)
         single.init_ligament(R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength, rho_l=RHO_L,
                              rho_v=RHO_V, seed=c.seed)
