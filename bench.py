@@ -137,6 +137,10 @@ def main():
     ap.add_argument("--form", default="single",
                     choices=["single", "batch", "precision", "shift", "convergence", "paper", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kinds", default="f64,f32,f16s,bf16s,f16m,bf16m",
+                    help="--form precision: storage kinds to run (f64 first: it is the reference)")
+    ap.add_argument("--cases", default="base,G-6,tau1",
+                    help="--form precision: cases to run (base, G-6, tau1)")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
                     help="mrt: the multiple-relaxation-time collision with the suggested rates "
                          "of d'Humieres et al. and s_j = 1/tau")
@@ -339,13 +343,14 @@ def study_precision(args, lbm, workloads, stream):
     import torch
 
     base = workloads.LARGE_FP32
-    cases = [base, dataclasses.replace(base, name="large G=-6.0", G=-6.0),
-             dataclasses.replace(base, name="large tau=1.0", tau=1.0)]
+    all_cases = {"base": base, "G-6": dataclasses.replace(base, name="large G=-6.0", G=-6.0),
+                 "tau1": dataclasses.replace(base, name="large tau=1.0", tau=1.0)}
+    cases = [all_cases[c] for c in args.cases.split(",")]
     out = []
     for spec in cases:
         rho_l, rho_v = lbm.lbm_coexistence(spec.G, spec.tau)
         res = {}
-        for storage in ("f64", "f32", "f16s", "bf16s", "f16m", "bf16m"):
+        for storage in args.kinds.split(","):
             print(f"# {spec.name} {storage}", file=sys.stderr, flush=True)
             r = _run_ligament(lbm, spec, storage, rho_l, rho_v, stream, spec.steps, every=10,
                               extra_after=1000)

@@ -455,21 +455,33 @@ int lbm_batch_diagnostics(lbm_batch *b, lbm_diag *out);
 /* Per-case FP64 export, as lbm_get_fields, for case `index`. */
 int lbm_batch_get_fields(lbm_batch *b, int32_t index, uint32_t mask, double *rho, double *u,
                          double *force, double *pop, int32_t on_device);
-/* Launch of the batched step (z chunk >= 4); the default is the 512-thread
- * run-time tile, shaped per case, with z chunks of 8 planes. */
+/* Launch of the batched step (z chunk >= 4; also resets the chunking to
+ * uniform chunks).  The default is the run-time tile of 1024 threads (512
+ * for FP64), shaped per case, with z chunks of 5 planes. */
 int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l);
 /*
- * Autotuner of the batched launch: time each tile shape and z chunk (4, 5,
- * 6, 8, 12, 16, 32, 64 and 128 planes) over the whole item list in the loop
- * lbm_batch_step runs (an even number of launches alternating between each
- * case's two lattices, after two warm-up launches) and keep the fastest.
- * The current lattices of the cases in the launch list are copied to a
- * temporary device buffer first (allocated and freed here) and restored at
- * the end, so the state is unchanged.  *best_mlups counts the nodes of the
- * cases that are not frozen.  Synchronous.
+ * Autotuner of the batched launch: time each tile shape with uniform z
+ * chunks (4, 5, 6, 8, 12, 16, 32, 64 and 128 planes) and with equal-cost
+ * chunks of 4, 8, 16 and 32 rounds (lbm_batch_set_chunking) over the whole
+ * item list in the loop lbm_batch_step runs (an even number of launches
+ * alternating between each case's two lattices, after two warm-up
+ * launches), and keep the fastest launch and chunking.  The current
+ * lattices of the cases in the launch list are copied to a temporary device
+ * buffer first (allocated and freed here) and restored at the end, so the
+ * state is unchanged.  *best_mlups counts the nodes of the cases that are
+ * not frozen.  Synchronous.
  */
 int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *best,
                        double *best_mlups);
+/*
+ * Chunking of the batched launch: rounds = 0 (the default) cuts every case
+ * into z chunks of the launch's zchunk; rounds > 0 sizes each case's chunks
+ * (at least 4 planes, an even split of its nz) so that every work item costs
+ * about the same, tile and ring nodes times planes, and the launch holds
+ * about `rounds` times as many items as the device runs at once.  Errors:
+ * INVALID_ARG (rounds < 0, or more items than the workspace was sized for).
+ */
+int lbm_batch_set_chunking(lbm_batch *b, int32_t rounds);
 int lbm_batch_set_graph_chunk(lbm_batch *b, int32_t chunk_steps);
 int lbm_batch_destroy(lbm_batch *b);
 

@@ -60,6 +60,10 @@ int validate_params(const lbm_params *p) {
         return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane holds more than 2^31 - 1 populations", p->nx, p->ny);
     if (n > int64_t(0x7fffffff))
         return fail(LBM_ERR_INVALID_ARG, "grid of %lld nodes exceeds 2^31 - 1 nodes", (long long)n);
+    // the step kernels address within a plane with 32-bit byte offsets
+    if (p->storage >= LBM_F64 && p->storage <= LBM_BF16M &&
+        int64_t(Q + 1) * p->nx * (int64_t(p->ny) + 31) * int64_t(elem_bytes(p->storage)) > int64_t(0xffffffff))
+        return fail(LBM_ERR_INVALID_ARG, "a %d x %d plane of this storage kind exceeds 4 GiB", p->nx, p->ny);
     if (!(p->tau > 0.5) || !isfinite(p->tau))
         return fail(LBM_ERR_INVALID_ARG, "tau must be finite and > 0.5 (got %g)", p->tau);
     if (!isfinite(p->G)) return fail(LBM_ERR_INVALID_ARG, "G must be finite");
@@ -1331,6 +1335,10 @@ struct lbm_batch {
     std::vector<uint8_t> dropped;
     uint32_t *counter;  // device step counter, as in lbm_ctx
     uint32_t dstep;
+    // > 0: per-case z chunks sized so that every work item costs about the
+    // same and the launch holds about `rounds` times as many items as the
+    // device runs at once; 0: every case uses the launch's zchunk.
+    int rounds;
 };
 
 namespace {
@@ -1469,6 +1477,33 @@ hipError_t batch_upload(lbm_batch *b) {
     };
     std::vector<Item> all;
     const lbm_launch &l = b->launch;
+    // z chunk per case: uniform, or (rounds > 0) about rounds x slots items
+    // of equal cost, cost per plane = tile + ring nodes
+    std::vector<int> zc_case(b->n, l.zchunk);
+    if (b->rounds > 0) {
+        double plane_cost = 0;
+        std::vector<double> area(b->n, 0.0);
+        std::vector<int64_t> tiles(b->n, 0);
+        for (int i = 0; i < b->n; ++i) {
+            if (b->dropped[i]) continue;
+            int tw, th;
+            tile_dims(l, b->p[i].nx, b->p[i].ny, &tw, &th);
+            tiles[i] = int64_t((b->p[i].nx + tw - 1) / tw) * ((b->p[i].ny + th - 1) / th);
+            area[i] = double(tw) * th + 2.0 * (tw + 2) + 2.0 * th;
+            plane_cost += double(tiles[i]) * b->p[i].nz * area[i];
+        }
+        int slots = launch_slots(b->tile_index, b->p[0].storage);
+        if (slots <= 0) slots = 512;
+        const double per_item = plane_cost / (double(b->rounds) * slots);
+        for (int i = 0; i < b->n; ++i) {
+            if (b->dropped[i]) continue;
+            const int nz = b->p[i].nz;
+            int zc = int(per_item / area[i] + 0.5);
+            zc = std::max(kBatchMinZchunk, std::min(zc, nz));
+            const int nch = (nz + zc - 1) / zc;
+            zc_case[i] = std::max(std::min(kBatchMinZchunk, nz), (nz + nch - 1) / nch);
+        }
+    }
     for (int i = 0; i < b->n; ++i) {
         StepArgs A;
         A.src = nullptr;
@@ -1479,7 +1514,7 @@ hipError_t batch_upload(lbm_batch *b) {
         tile_dims(l, A.nx, A.ny, &A.tile_w, &A.tile_h);
         A.tiles_x = (A.nx + A.tile_w - 1) / A.tile_w;
         A.tiles_y = (A.ny + A.tile_h - 1) / A.tile_h;
-        A.zchunk = l.zchunk < A.nz ? l.zchunk : A.nz;
+        A.zchunk = zc_case[i] < A.nz ? zc_case[i] : A.nz;
         A.nchunks = (A.nz + A.zchunk - 1) / A.zchunk;
         A.pop_stride = b->lay[i].S;
         A.row_stride = b->lay[i].R;
@@ -1612,13 +1647,15 @@ hipError_t batch_after_check(lbm_batch *b) {
 
 lbm_launch batch_default_launch(int n, const lbm_params *p) {
     (void)n;
-    (void)p;
     lbm_launch l;
     l.tile_x = 0;  // each case gets its own full-row tile shape
-    l.tile_y = 512;
-    // Measured on MI355X over the 51 live cases of the 64-ligament batch:
-    // z chunks of 5-8 planes within 1% of each other, 16 planes 4% slower.
-    l.zchunk = 8;
+    // Measured on MI355X over the 51 live cases of the 64-ligament batch
+    // (FP32, whole-row tiles with their ghost ring): 1024-thread tiles with
+    // z chunks of 5 planes 0.779 ms per step, 8 planes 0.789, 16 planes
+    // 0.825; 512-thread tiles 0.796 (5 planes) to 0.825 (16).  FP64 keeps 512
+    // threads (its kernel spills with 1024).
+    l.tile_y = p[0].storage == LBM_F64 ? 512 : 1024;
+    l.zchunk = 5;
     return l;
 }
 
@@ -1658,6 +1695,7 @@ int lbm_batch_create(int32_t ncases, const lbm_params *p, void *d_workspace, siz
     b->d_slices = reinterpret_cast<unsigned long long *>(b->ws + B.off_slices);
     b->counter = reinterpret_cast<uint32_t *>(b->ws + B.off_counter);
     b->dstep = 0;
+    b->rounds = 0;
     b->item_capacity = B.item_capacity;
     b->parity = 0;
     b->step = 0;
@@ -1861,6 +1899,7 @@ int lbm_batch_set_launch(lbm_batch *b, const lbm_launch *l) {
     if (l->zchunk < kBatchMinZchunk) return fail(LBM_ERR_INVALID_ARG, "batched zchunk must be >= %d", kBatchMinZchunk);
     b->launch = *l;
     b->tile_index = find_tile(l->tile_x, l->tile_y);
+    b->rounds = 0;
     hipError_t e = batch_upload(b);
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_set_launch");
     return LBM_OK;
@@ -1871,11 +1910,30 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     if (st != LBM_OK) return st;
     if (!b->initialized) return fail(LBM_ERR_STATE, "batch not initialised");
     if (steps_per_candidate < 1) return fail(LBM_ERR_INVALID_ARG, "steps_per_candidate must be >= 1");
-    // short chunks matter here: the batch's grids are narrow, so their
-    // workgroups are few per case and a chunk of 5-6 planes can beat 8
+    // Candidates: every tile with uniform z chunks, and with equal-cost
+    // chunks of 4 to 32 rounds (lbm_batch_set_chunking).  Short chunks
+    // matter here: the batch's grids are narrow, so their workgroups are few
+    // per case, and many short items balance the launch.
+    struct Cand {
+        lbm_launch l;
+        int rounds;
+    };
+    std::vector<Cand> cands;
     const int zcs[] = {4, 5, 6, 8, 12, 16, 32, 64, 128};
-    const lbm_launch orig = b->launch;
-    lbm_launch bl = orig;
+    const int rounds[] = {4, 8, 16, 32};
+    for (int ti = 0; ti < num_tiles(); ++ti) {
+        if (!tile_has_storage(ti, b->p[0].storage)) continue;
+        lbm_launch l;
+        tile_shape(ti, &l.tile_x, &l.tile_y);
+        for (int zc : zcs) {
+            l.zchunk = zc;
+            cands.push_back(Cand{l, 0});
+        }
+        l.zchunk = kBatchMinZchunk;
+        for (int r : rounds) cands.push_back(Cand{l, r});
+    }
+    lbm_launch bl = b->launch;
+    int brounds = b->rounds;
     double best_t = INFINITY;
     // Candidates are timed in the loop lbm_batch_step runs: launches that
     // alternate between the two lattices of every case (an even number).
@@ -1905,41 +1963,38 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     double nodes = 0;
     for (int i = 0; i < b->n; ++i)
         if (fz[i] == 0) nodes += double(b->p[i].nx) * b->p[i].ny * b->p[i].nz;
-    for (int ti = 0; ti < num_tiles() && e == hipSuccess; ++ti) {
-        if (!tile_has_storage(ti, b->p[0].storage)) continue;
-        lbm_launch l;
-        tile_shape(ti, &l.tile_x, &l.tile_y);
-        for (int zc : zcs) {
-            l.zchunk = zc;
-            b->launch = l;
-            b->tile_index = ti;
-            e = batch_upload(b);
-            if (e != hipSuccess) {
-                if (e == hipErrorInvalidValue) e = hipSuccess;  // more items than the table holds
-                continue;
-            }
-            auto two_steps = [&]() {
-                hipError_t r = hipSuccess;
-                if (b->nitems > 0)
-                    for (int q = 0; q < 2 && r == hipSuccess; ++q)
-                        r = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems,
-                                              b->d_frozen, b->parity ^ q, b->counter,
-                                              uint32_t(b->step) - b->dstep, b->stream);
-                return r;
-            };
-            e = two_steps();  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            for (int s = 0; s < pairs && e == hipSuccess; ++s) e = two_steps();
-            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
-            const double t = ms / (2.0 * pairs);
-            if (t < best_t) {
-                best_t = t;
-                bl = l;
-            }
+    for (const Cand &c : cands) {
+        if (e != hipSuccess) break;
+        const int ti = find_tile(c.l.tile_x, c.l.tile_y);
+        b->launch = c.l;
+        b->tile_index = ti;
+        b->rounds = c.rounds;
+        e = batch_upload(b);
+        if (e != hipSuccess) {
+            if (e == hipErrorInvalidValue) e = hipSuccess;  // more items than the table holds
+            continue;
+        }
+        auto two_steps = [&]() {
+            hipError_t r = hipSuccess;
+            if (b->nitems > 0)
+                for (int q = 0; q < 2 && r == hipSuccess; ++q)
+                    r = launch_step_batch(ti, b->p[0].storage, b->d_cases, b->d_items, b->nitems, b->d_frozen,
+                                          b->parity ^ q, b->counter, uint32_t(b->step) - b->dstep, b->stream);
+            return r;
+        };
+        e = two_steps();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int s = 0; s < pairs && e == hipSuccess; ++s) e = two_steps();
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        const double t = ms / (2.0 * pairs);
+        if (t < best_t) {
+            best_t = t;
+            bl = c.l;
+            brounds = c.rounds;
         }
     }
     if (saved) {
@@ -1955,11 +2010,29 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps_per_candidate, lbm_launch *be
     if (e1) (void)hipEventDestroy(e1);
     b->launch = bl;
     b->tile_index = find_tile(bl.tile_x, bl.tile_y);
+    b->rounds = brounds;
     if (e == hipSuccess) e = batch_upload(b);
     if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_autotune");
     batch_release_graph(b);
     if (best) *best = bl;
     if (best_mlups) *best_mlups = nodes / (best_t * 1e-3) / 1e6;
+    return LBM_OK;
+}
+
+int lbm_batch_set_chunking(lbm_batch *b, int32_t rounds) {
+    int st = batch_check(b);
+    if (st != LBM_OK) return st;
+    if (rounds < 0) return fail(LBM_ERR_INVALID_ARG, "rounds must be >= 0");
+    const int old = b->rounds;
+    b->rounds = rounds;
+    hipError_t e = batch_upload(b);
+    if (e == hipErrorInvalidValue) {
+        b->rounds = old;
+        (void)batch_upload(b);
+        return fail(LBM_ERR_INVALID_ARG, "chunking gives more work items than the workspace holds");
+    }
+    if (e != hipSuccess) return batch_device_fail(b, e, "lbm_batch_set_chunking");
+    batch_release_graph(b);
     return LBM_OK;
 }
 

@@ -105,29 +105,30 @@ __host__ __device__ inline uint32_t hash32(uint32_t x) {
 // smaller than the 16-bit spacing survive on average instead of being
 // rounded away step after step (round-to-nearest holds a slowly changing
 // population at the same stored value, and a slowly growing flow with it).
-// Population a takes the 8 random bits at offset 4 ((a - 1) mod 6) of word
-// (a - 1) / 6 (overlapping windows, each uniform); they are added, with half a unit of the
-// byte, at the top of the FP32 mantissa bits the 16-bit type drops, and the
-// sum is truncated.  Below the half-precision normal range (|h| < 2^-14, a
-// spacing of 2^-24) F16M truncates toward zero.
+// Population a takes a window of D random bits (D = the number of FP32
+// mantissa bits the 16-bit type drops: 13 for half, 16 for bfloat16) from
+// word (a - 1) / 6 at offset ((a - 1) mod 6) (32 - D) / 5 (overlapping
+// windows, each uniform), adds it to the FP32 bit pattern and truncates.
+// Below the half-precision normal range (|h| < 2^-14, a spacing of 2^-24)
+// F16M truncates toward zero.
 template <typename Tr>
 __device__ inline float round_moving_sr(const float (&h)[Q], typename Tr::T (&out)[Q], const uint32_t (&rnd)[3]) {
     constexpr int D = Tr::kDropBits;
     float sum = 0.0f;
 #pragma unroll
     for (int a = 1; a < Q; ++a) {
-        const uint32_t byte = __builtin_amdgcn_ubfe(rnd[(a - 1) / 6], 4 * ((a - 1) % 6), 8);
-        const uint32_t bits = __float_as_uint(h[a]) + ((byte << (D - 8)) | (1u << (D - 9)));
-        float r;
+        const uint32_t r = __builtin_amdgcn_ubfe(rnd[(a - 1) / 6], ((a - 1) % 6) * (32 - D) / 5, D);
+        const uint32_t bits = __float_as_uint(h[a]) + r;
+        float v;
         if constexpr (D == 16) {  // bfloat16: the upper half of the FP32 pattern
             const uint32_t t = bits & 0xFFFF0000u;
             out[a] = __builtin_bit_cast(typename Tr::T, static_cast<uint16_t>(t >> 16));
-            r = __uint_as_float(t);
+            v = __uint_as_float(t);
         } else {  // half: truncating conversion of the perturbed value
             out[a] = __builtin_amdgcn_cvt_pkrtz(__uint_as_float(bits), 0.0f)[0];
-            r = static_cast<float>(out[a]);
+            v = static_cast<float>(out[a]);
         }
-        sum = (a == 1) ? r : sum + r;
+        sum = (a == 1) ? v : sum + v;
     }
     return sum;
 }

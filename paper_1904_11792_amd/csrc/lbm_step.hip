@@ -58,8 +58,6 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     const int64_t plane = A.plane_stride;
     const int rowst = A.row_stride;
-    const T *__restrict__ src = static_cast<const T *>(A.src);
-    T *__restrict__ dst = static_cast<T *>(A.dst);
     const int S = int(A.pop_stride);
     const C rho0 = C(A.rho0), inv_rho0 = C(1.0 / A.rho0);
     const C G = C(A.G), tau = C(A.tau), omega = C(1.0 / A.tau);
@@ -141,16 +139,44 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
                        row_offset(wrapi(rgy + 1, ny), rowst, rsh, nx)};
     const int RYR = MR ? row_offset(rgy, rowst / 2, rsh, nx) : 0;
 
-    // The plane offset is 64-bit and wave-uniform; the offset within a plane
-    // is 32-bit (the host keeps 19 nx ny below 2^31).
-    auto gather = [&](int zc, const int(&XX)[3], const int(&YY)[3], int YYR, C(&f)[Q]) {
-        const T *Zp[3] = {src + wrapi(zc - 1, nz) * plane, src + zc * plane, src + wrapi(zc + 1, nz) * plane};
-        // Opaque copies of the row offsets: without them the compiler keeps
-        // 19 loop-invariant 64-bit addresses per thread (38 VGPRs) across the
-        // march instead of forming each address at its load.
-        int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]}, yr = YYR;
-        asm volatile("" : "+v"(yy[0]), "+v"(yy[1]), "+v"(yy[2]), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]));
-        if constexpr (MR) asm volatile("" : "+v"(yr));
+    // Addresses: a wave-uniform 64-bit part (plane and population, scalar
+    // registers) plus a 32-bit byte offset within the plane (the host keeps
+    // a plane below 4 GiB).  The byte offsets of the nine (row, column)
+    // combinations a pull reads from -- index (1 - c_y) 3 + (1 - c_x) --
+    // and of the FP32 rest population are fixed for the whole march, so a
+    // load or store needs no vector arithmetic for its address.
+    // The bfloat16 kernels would spill with eighteen offsets held over the
+    // march; they keep the three row and three column offsets instead and
+    // form the nine byte offsets at each gather (one add and shift each).
+    using u32 = uint32_t;
+    constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M);
+    auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
+        int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
+        if constexpr (!kHoldOffsets)  // opaque copies: formed here, not hoisted
+            asm volatile("" : "+v"(yy[0]), "+v"(yy[1]), "+v"(yy[2]), "+v"(xx[0]), "+v"(xx[1]), "+v"(xx[2]));
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[r * 3 + c] = u32(yy[r] + xx[c]) * u32(sizeof(T));
+    };
+    u32 OT[9], OR[9];
+    if constexpr (kHoldOffsets) {
+        offsets9(X, Y, OT);
+        offsets9(RX, RY, OR);
+    }
+    const u32 OTR = MR ? u32(YR + X[1]) * 4u : 0u, ORR = MR ? u32(RYR + RX[1]) * 4u : 0u;
+    const int64_t plane_b = plane * int64_t(sizeof(T));
+    const u32 S_b = u32(S) * u32(sizeof(T));
+    const char *const srcb = static_cast<const char *>(A.src);
+    char *const dstb = static_cast<char *>(A.dst);
+
+    auto gather = [&](int zc, const u32(&o_held)[9], const int(&XX)[3], const int(&YY)[3], u32 orest, C(&f)[Q]) {
+        const char *zp[3] = {srcb + wrapi(zc - 1, nz) * plane_b, srcb + zc * plane_b,
+                             srcb + wrapi(zc + 1, nz) * plane_b};
+        u32 o[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) o[q] = o_held[q];
+        if constexpr (!kHoldOffsets) offsets9(XX, YY, o);
         // All 19 loads are issued before the first use: the scheduler would
         // otherwise interleave load, wait and convert for 16-bit storage.
         // With PRIO the wave issues them at raised priority, ahead of other
@@ -164,9 +190,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             if (MR && a == 0)
-                rest = reinterpret_cast<const float *>(Zp[1])[yr + xx[1]];
+                rest = *reinterpret_cast<const float *>(zp[1] + orest);
             else
-                raw[a] = (Zp[1 - kCZ[a]] + pop_slot(a, MR) * S)[yy[1 - kCY[a]] + xx[1 - kCX[a]]];
+                raw[a] = *reinterpret_cast<const T *>(zp[1 - kCZ[a]] + u32(pop_slot(a, MR)) * S_b +
+                                                      o[(1 - kCY[a]) * 3 + (1 - kCX[a])]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
@@ -189,12 +216,12 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // psi of plane zc for the tile (pops kept in f) and the ring, into window slot s.
     auto load_plane = [&](int zc, int s, C(&f)[Q]) {
         if (inside) {
-            gather(zc, X, Y, YR, f);
+            gather(zc, OT, X, Y, OTR, f);
             put(s, ly + 1, lx + 1, pseudo_potential(node_density(f), rho0, inv_rho0));
         }
         if (ring) {
             C g[Q];
-            gather(zc, RX, RY, RYR, g);
+            gather(zc, OR, RX, RY, ORR, g);
             put(s, ry + 1, rx + 1, pseudo_potential(node_density(g), rho0, inv_rho0));
         }
     };
@@ -219,28 +246,27 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         };
         C Fx, Fy, Fz;
         sc_force<C>(W(s0, ly + 1, lx + 1), G, P, Fx, Fy, Fz);
-        T *const zb = dst + zc * plane;
-        int o = Y[1] + X[1];
+        char *const zb = dstb + zc * plane_b;
         if constexpr (MR) {
             T out[Q];
             // random words of this node and step (node index as in the canonical layout)
             const uint32_t node = (uint32_t(zc) * uint32_t(ny) + uint32_t(gy)) * uint32_t(nx) + uint32_t(gx);
             const uint32_t rnd[3] = {hash32(node ^ skey[0]), hash32(node ^ skey[1]), hash32(node ^ skey[2])};
             collide_shifted<Tr>(f, out, Fx, Fy, Fz, tau, omega, rho_ref, rnd);
-            int orr = YR + X[1];
-            asm volatile("" : "+v"(o), "+v"(orr));  // as in gather: form each store address here
-            __builtin_nontemporal_store(f[0], &reinterpret_cast<float *>(zb)[orr]);
+            __builtin_nontemporal_store(f[0], reinterpret_cast<float *>(zb + OTR));
+            const u32 oc = kHoldOffsets ? OT[4] : u32(Y[1] + X[1]) * u32(sizeof(T));
 #pragma unroll
-            for (int a = 1; a < Q; ++a) __builtin_nontemporal_store(out[a], &(zb + pop_slot(a, MR) * S)[o]);
+            for (int a = 1; a < Q; ++a)
+                __builtin_nontemporal_store(out[a], reinterpret_cast<T *>(zb + u32(pop_slot(a, MR)) * S_b + oc));
         } else {
             if constexpr (MRT)
                 collide_mrt<C>(f, Fx, Fy, Fz, rates);
             else
                 collide<C>(f, Fx, Fy, Fz, tau, omega);
-            asm volatile("" : "+v"(o));  // as in gather: form each store address here
+            const u32 oc = kHoldOffsets ? OT[4] : u32(Y[1] + X[1]) * u32(sizeof(T));
 #pragma unroll
             for (int a = 0; a < Q; ++a)
-                __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), &(zb + a * S)[o]);
+                __builtin_nontemporal_store(Tr::encode(f[a], shift[a]), reinterpret_cast<T *>(zb + u32(a) * S_b + oc));
         }
     };
 

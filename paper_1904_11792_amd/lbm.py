@@ -142,6 +142,7 @@ _SIGS = {
     "lbm_batch_get_fields": (ctypes.c_int, [_vp, _i32, _u32, _vp, _vp, _vp, _vp, _i32]),
     "lbm_batch_set_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
     "lbm_batch_set_graph_chunk": (ctypes.c_int, [_vp, _i32]),
+    "lbm_batch_set_chunking": (ctypes.c_int, [_vp, _i32]),
     "lbm_batch_autotune": (ctypes.c_int, [_vp, _i32, _P(lbm_launch), _P(_d)]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
 }
@@ -562,6 +563,10 @@ class Batch:
 
     def set_graph_chunk(self, chunk_steps: int) -> None:
         _check(_lib.lbm_batch_set_graph_chunk(self.handle, chunk_steps))
+
+    def set_chunking(self, rounds: int) -> None:
+        """0: uniform z chunks of the launch; > 0: equal-cost chunks, about `rounds` rounds."""
+        _check(_lib.lbm_batch_set_chunking(self.handle, int(rounds)))
 
     def autotune(self, steps_per_candidate: int = 3):
         l = lbm_launch()

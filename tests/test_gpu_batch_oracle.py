@@ -6,8 +6,9 @@ the device case table.  Here nine cases of the 64-ligament workload
 (uneven grids 24^2 x 58 ... 38^2 x 113, tau 0.64 ... 1.13, G -5.94 ... -5.05;
 cases the oracle finds stable over 200 steps)
 plus one case that diverges within a few steps run through lbm_batch_* at
-the launches the benchmark uses (512-thread run-time tiles, z chunks of 6
-and 8 planes), in captured graphs of 20 steps.  After 100 steps the
+the launches the benchmark's autotuner chooses among (run-time tiles of 512
+and 1024 threads, uniform z chunks of 5 to 8 planes, and equal-cost chunks
+of 8 rounds), in captured graphs of 20 steps.  After 100 steps the
 diagnostics freeze the diverged case and drop it from the launch list
 (the item list and the graph are rebuilt); 100 more steps follow.  Every
 live case is then compared with the oracle run for 200 steps from the same
@@ -67,8 +68,9 @@ def _relerr(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))
 
 
-@pytest.mark.parametrize("storage,zchunk", [("f32", 6), ("f32", 8), ("f64", 8)])
-def test_batch_matches_oracle_across_graphs_and_compaction(lbm, reference, storage, zchunk):
+@pytest.mark.parametrize("storage,launch,rounds", [
+    ("f32", (0, 512, 6), 0), ("f32", (0, 1024, 5), 0), ("f32", (0, 1024, 4), 8), ("f64", (0, 512, 8), 0)])
+def test_batch_matches_oracle_across_graphs_and_compaction(lbm, reference, storage, launch, rounds):
     import torch
 
     d = DIVERGING
@@ -79,7 +81,8 @@ def test_batch_matches_oracle_across_graphs_and_compaction(lbm, reference, stora
                                    rho_l=d["rho_l"], rho_v=d["rho_v"]))
     stream = torch.cuda.Stream()
     b = lbm.Batch(params, stream=stream)
-    b.set_launch(0, 512, zchunk)
+    b.set_launch(*launch)
+    b.set_chunking(rounds)
     b.set_graph_chunk(20)
     b.init(specs)
     b.step(100)
@@ -98,6 +101,6 @@ def test_batch_matches_oracle_across_graphs_and_compaction(lbm, reference, stora
             err = _relerr(got, ref.sum(axis=0))
             assert err < 1e-5, (i, err)
         worst = max(worst, err)
-    print(f"{storage} z chunk {zchunk}: worst error over {len(reference)} cases {worst:.2e}")
+    print(f"{storage} launch {launch} rounds {rounds}: worst error over {len(reference)} cases {worst:.2e}")
     assert b.diagnostics()[-1]["nonfinite"] > 0  # the frozen case stays frozen
     b.close()
