@@ -83,7 +83,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, storage: str) -> dict:
 
     spec = __import__("workloads").LARGE_FP32
     copy_kib = spec.n * BYTES_PER_NODE[storage] / 1024.0
-    tag = f"k_step<{STORAGE_ID[storage]},"
+    tag = f"k_step_bgk<{STORAGE_ID[storage]},"
 
     def per_dispatch(path, counter):
         step, copy = [], []
@@ -269,9 +269,41 @@ def main():
     }
     print(f"# {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s",
           file=sys.stderr, flush=True)
+    if args.storage == "f32" and mrt is None and not args.grid and not args.slab and not args.launch:
+        # the metric's second half: 16-bit storage against FP32 on the same
+        # workload, timed the same way (its error against FP64 is the study
+        # of --form precision)
+        lat.close()
+        out["fp16_store"] = fp16_store_line(lbm, spec, rho_l, rho_v, stream, args, ms_per_step)
     if not args.no_cpu_baseline and mrt is None and not args.grid:
         out["cpu_baseline"] = cpu_baseline(spec, rho_l, rho_v)
     print(json.dumps(out), flush=True)
+
+
+def fp16_store_line(lbm, spec, rho_l, rho_v, stream, args, ms_f32):
+    """Step throughput of the F16M storage (moving populations in half
+    precision, stochastically rounded; rest population in FP32) on the
+    benchmark workload: ms per step, MLUPS, HBM fraction at its 80 B per
+    node, and the speed-up over the FP32 step of the same run."""
+    import torch
+
+    lat = lbm.Lattice(spec.nx, spec.ny, spec.nz, spec.tau, spec.G, storage="f16m", rho_ref=rho_v,
+                      stream=stream)
+    lat.init_ligament(R0=spec.R0, amp_rel=spec.amp_rel, wavelength=spec.wavelength,
+                      rho_l=rho_l, rho_v=rho_v, noise_amp=spec.noise_amp, seed=spec.seed)
+    lat.step(args.warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    lat.close()
+    gbs = 2 * BYTES_PER_NODE["f16m"] * spec.n / (ms * 1e-3) / 1e9
+    return {"storage": "f16m", "ms_per_step": round(ms, 4), "MLUPS": round(spec.n / ms / 1e3, 1),
+            "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "speedup_vs_f32": round(ms_f32 / ms, 3), "error_study": "bench.py --form precision"}
 
 
 def sweep(lat, spec, stream, storage):

@@ -33,19 +33,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sc_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source,
+# loaded instead when ORACLE_SANITIZED=1 (the process must then preload the
+# ASan runtime, see tests/test_oracle_sanitized.py)
+_SO_SAN = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
 
 Q = 19
 
 
-def build() -> str:
-    """Compile sc_oracle.c with gcc into oracle/liboracle.so (always rebuilds)."""
-    tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-shared", "-fPIC",
+def build(sanitize: bool = False) -> str:
+    """Compile sc_oracle.c with gcc into oracle/liboracle.so (always rebuilds);
+    with sanitize=True into oracle/liboracle_san.so, instrumented with
+    AddressSanitizer and UndefinedBehaviorSanitizer (every report fatal)."""
+    out = _SO_SAN if sanitize else _SO
+    tmp = out + ".tmp"
+    extra = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+             if sanitize else [])
+    cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-shared", "-fPIC", *extra,
            _SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, out)
+    return out
 
 
 def lib():
@@ -53,9 +62,11 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO):
-        build()
-    L = ctypes.CDLL(_SO)
+    sanitized = os.environ.get("ORACLE_SANITIZED") == "1"
+    path = _SO_SAN if sanitized else _SO
+    if not os.path.exists(path):
+        build(sanitize=sanitized)
+    L = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     i32p = ctypes.POINTER(ctypes.c_int32)

@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbm.so")
+# LBM_LIBRARY names another build of the same library (the host-sanitized
+# one of build.py), else the in-tree liblbm.so
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_HERE, "liblbm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
