@@ -25,6 +25,19 @@ __host__ __device__ constexpr double weight(int a) {
     return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
+// 1.0f in a register whose value the compiler does not see: a fused
+// multiply-add with it is an addition rounded once, and one that takes a
+// half-precision operand directly (v_fma_mix_f32), where a plain addition
+// converts the half first (two instructions).
+__device__ inline float opaque_one() {
+    float o = 1.0f;
+    asm("" : "+v"(o));
+    return o;
+}
+// acc + v in FP32 for a 16-bit storage value v (the conversion is exact).
+__device__ inline float add16(_Float16 v, float acc) { return __builtin_fmaf(static_cast<float>(v), opaque_one(), acc); }
+__device__ inline float add16(__bf16 v, float acc) { return static_cast<float>(v) + acc; }
+
 enum StorageKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF16M = 4, kBF16M = 5 };
 constexpr int kNumStorage = 6;
 
@@ -59,7 +72,7 @@ template <> struct Storage<kF16S> {
     using T = _Float16;
     using C = float;
     static constexpr bool kShifted = true, kMassRest = false;
-    __device__ static C decode(T v, C shift) { return shift + static_cast<float>(v); }
+    __device__ static C decode(T v, C shift) { return add16(v, shift); }
     __device__ static T encode(C f, C shift) { return static_cast<_Float16>(f - shift); }
 };
 template <> struct Storage<kBF16S> {
@@ -111,26 +124,37 @@ __host__ __device__ inline uint32_t hash32(uint32_t x) {
 // windows, each uniform), adds it to the FP32 bit pattern and truncates.
 // Below the half-precision normal range (|h| < 2^-14, a spacing of 2^-24)
 // F16M truncates toward zero.
+// FP32 sum of the 18 moving populations as stored (slots 1..18 of v), in the
+// order 1, 2, ..., 18.  The values are multiples of 2^-24 (half) or carry 8
+// significant bits (bfloat16), so the sum is exact unless their magnitudes
+// span more than the 24 bits of FP32.
+template <typename T>
+__device__ inline float moving_sum16(const T (&v)[Q]) {
+    float s = static_cast<float>(v[1]);
+#pragma unroll
+    for (int a = 2; a < Q; ++a) s = add16(v[a], s);
+    return s;
+}
+
 template <typename Tr>
 __device__ inline float round_moving_sr(const float (&h)[Q], typename Tr::T (&out)[Q], const uint32_t (&rnd)[3]) {
+    using T = typename Tr::T;
     constexpr int D = Tr::kDropBits;
-    float sum = 0.0f;
+    auto perturbed = [&](int a) -> uint32_t {
+        return __float_as_uint(h[a]) + __builtin_amdgcn_ubfe(rnd[(a - 1) / 6], ((a - 1) % 6) * (32 - D) / 5, D);
+    };
 #pragma unroll
-    for (int a = 1; a < Q; ++a) {
-        const uint32_t r = __builtin_amdgcn_ubfe(rnd[(a - 1) / 6], ((a - 1) % 6) * (32 - D) / 5, D);
-        const uint32_t bits = __float_as_uint(h[a]) + r;
-        float v;
+    for (int a = 1; a < Q; a += 2) {
         if constexpr (D == 16) {  // bfloat16: the upper half of the FP32 pattern
-            const uint32_t t = bits & 0xFFFF0000u;
-            out[a] = __builtin_bit_cast(typename Tr::T, static_cast<uint16_t>(t >> 16));
-            v = __uint_as_float(t);
-        } else {  // half: truncating conversion of the perturbed value
-            out[a] = __builtin_amdgcn_cvt_pkrtz(__uint_as_float(bits), 0.0f)[0];
-            v = static_cast<float>(out[a]);
+            out[a] = __builtin_bit_cast(T, static_cast<uint16_t>(perturbed(a) >> 16));
+            out[a + 1] = __builtin_bit_cast(T, static_cast<uint16_t>(perturbed(a + 1) >> 16));
+        } else {  // half: truncating conversion of the perturbed values, two at a time
+            const auto p = __builtin_amdgcn_cvt_pkrtz(__uint_as_float(perturbed(a)), __uint_as_float(perturbed(a + 1)));
+            out[a] = static_cast<T>(p[0]);
+            out[a + 1] = static_cast<T>(p[1]);
         }
-        sum = (a == 1) ? v : sum + v;
     }
-    return sum;
+    return moving_sum16(out);
 }
 
 // Slots of 16-bit elements per node and population index -> slot: with an
@@ -179,9 +203,9 @@ __device__ inline void sc_force(C psi_c, C G, const PsiAt &P, C &Fx, C &Fy, C &F
 
 // BGK relaxation (Eq. 3, forcing term zero) towards f^eq(rho, u') (Eq. 2)
 // with u' = (j + tau F) / rho (Eqs. 4 and 6).  In place on f.
+// rho is density(f), passed in by callers that already have it.
 template <typename C>
-__device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
-    const C rho = density(f);
+__device__ inline void collide(C (&f)[Q], C rho, C Fx, C Fy, C Fz, C tau, C omega) {
     const C jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
     const C jy = (f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10]) + (f[15] - f[16]) + (f[17] - f[18]);
     const C jz = (f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14]) + (f[15] - f[16]) - (f[17] - f[18]);
@@ -221,29 +245,24 @@ __device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
     f[0] = rho - moving;
 }
 
+template <typename C>
+__device__ inline void collide(C (&f)[Q], C Fx, C Fy, C Fz, C tau, C omega) {
+    collide<C>(f, density(f), Fx, Fy, Fz, tau, omega);
+}
+
 // The same BGK relaxation for the shifted variables h_a = f_a - w_a rho_ref
-// of the kMassRest storage kinds.  m = rho - rho_ref is the sum of the h_a
-// (the 18 stored 16-bit values first, whose FP32 sum is exact unless their
-// magnitudes span more than 24 bits, then the FP32 rest); j = sum c_a h_a
-// (sum_a c_a w_a = 0); the equilibrium minus the shift is
+// of the kMassRest storage kinds.  m = rho - rho_ref is the sum of the h_a,
+// passed in (moving_sum16 of the stored values plus the FP32 rest);
+// j = sum c_a h_a (sum_a c_a w_a = 0); the equilibrium minus the shift is
 // w_a (m + rho (4.5 (c.u')^2 - 1.5 u'^2)) +- 3 w_a rho c.u'.  The moving
 // populations leave stochastically rounded to the storage type (`out`,
 // slots 1..18, round_moving_sr with the node's random words `rnd`); the rest
-// population becomes m minus their exact FP32 sum, so the node's stored mass
-// is m to within one FP32 rounding.
+// population becomes m minus their FP32 sum (exact as a rule), so the node's
+// stored mass is m to within one FP32 rounding.
 template <typename Tr>
-__device__ inline float shifted_excess(const float (&h)[Q]) {
-    float s = h[1];
-#pragma unroll
-    for (int a = 2; a < Q; ++a) s += h[a];
-    return s + h[0];
-}
-
-template <typename Tr>
-__device__ inline void collide_shifted(float (&h)[Q], typename Tr::T (&out)[Q], float Fx, float Fy, float Fz,
-                                       float tau, float omega, float rho_ref, const uint32_t (&rnd)[3]) {
+__device__ inline void collide_shifted(float (&h)[Q], float m, typename Tr::T (&out)[Q], float Fx, float Fy,
+                                       float Fz, float tau, float omega, float rho_ref, const uint32_t (&rnd)[3]) {
     using C = float;
-    const C m = shifted_excess<Tr>(h);
     const C rho = rho_ref + m;
     const C jx = (h[1] - h[2]) + (h[7] - h[8]) + (h[9] - h[10]) + (h[11] - h[12]) + (h[13] - h[14]);
     const C jy = (h[3] - h[4]) + (h[7] - h[8]) - (h[9] - h[10]) + (h[15] - h[16]) + (h[17] - h[18]);

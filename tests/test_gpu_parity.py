@@ -289,6 +289,35 @@ def test_fp32_rest_round_trip_and_mass_preserving_import(lbm, storage):
     assert np.allclose(back.sum(axis=0), g.sum(axis=0), rtol=2e-7, atol=0)
 
 
+@pytest.mark.parametrize("storage", ["f16m", "bf16m"])
+def test_fp32_rest_keeps_each_node_mass(lbm, oracle_mod, storage):
+    """One step of an FP32-rest kind keeps every node's mass: the values a
+    node stores in its collision (moving populations rounded to 16 bits, the
+    rest population set from the mass) sum to the node's mass before it, up
+    to FP32 rounding of that mass and of the rest (bar: 2^-22 of the
+    magnitudes involved).  A larger difference would mean the rest is taken
+    against a sum that is not the exact sum of the stored 16-bit values."""
+    s = workloads.SMALL_FP64
+    _, lat = _ligament_pair(lbm, oracle_mod, s.nx, s.ny, s.nz, s.tau, s.G, storage=storage,
+                            R0=s.R0, amp_rel=s.amp_rel, wavelength=s.wavelength)
+    lat.step(40)  # interfaces in motion
+    cx, cy, cz, w = oracle_mod.lattice()
+    before = lat.populations().cpu().numpy()
+    lat.step(1)
+    after = lat.populations().cpu().numpy()
+    # exported populations are f_a(x) after streaming: the values node x
+    # collided and sent on are after_a(x + c_a)
+    collided = np.stack([np.roll(after[a], (-cz[a], -cy[a], -cx[a]), axis=(0, 1, 2)) for a in range(19)])
+    m = before.sum(axis=0)
+    eps = collided.sum(axis=0) - m
+    shift = (w * RHO_V).astype(np.float32).astype(np.float64)
+    mag = np.abs(m - shift.sum()) + np.abs(collided[1:] - shift[1:, None, None, None]).sum(axis=0)
+    ratio = np.abs(eps) / np.maximum(mag, 1e-30)
+    print(f"{storage}: max |node mass change| {np.abs(eps).max():.3e}, "
+          f"max relative to the magnitudes {ratio.max():.3e} (2^-22 = {2.0 ** -22:.3e})")
+    assert np.all(np.abs(eps) <= 2.0 ** -22 * mag + 1e-15)
+
+
 @pytest.mark.parametrize("nx", [301, 480])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_run_time_tiles_on_wide_grid(lbm, oracle_mod, storage, nx):
