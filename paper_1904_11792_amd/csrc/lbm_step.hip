@@ -43,7 +43,8 @@ namespace lbm {
 // data format, no swizzle, no per-lane index).  Measured on MI355X with the
 // step on 256 x 256 x 1024: buffer access makes FP64 8% faster, but FP32,
 // FP16S and F16M 2-5% slower, although it removes 55-60 vector instructions
-// per node; so only FP64 uses it.
+// per node; so FP64 uses it, and the other kinds only for the loads of the
+// batched launch.
 template <bool BUF>
 struct PlaneRef;
 
@@ -209,7 +210,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // march; they keep the three row and three column offsets instead and
     // form the nine byte offsets at each gather (one add and shift each).
     using u32 = uint32_t;
-    using Plane = PlaneRef<ST == kF64>;
+    // Loads of the batched launch (PRIO false) go through buffer resources
+    // too: measured 2% faster there for FP32, while single grids are faster
+    // with global loads.
+    using SrcPlane = PlaneRef<ST == kF64 || !PRIO>;
+    using DstPlane = PlaneRef<ST == kF64>;
     constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M);
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
         int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
@@ -232,8 +237,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     char *const dstb = static_cast<char *>(A.dst);
 
     auto gather = [&](int zc, const u32(&o_held)[9], const int(&XX)[3], const int(&YY)[3], u32 orest, C(&f)[Q]) -> C {
-        const Plane pz[3] = {Plane(srcb + wrapz(zc - 1) * plane_b), Plane(srcb + zc * plane_b),
-                             Plane(srcb + wrapz(zc + 1) * plane_b)};  // index 1 + dz
+        const SrcPlane pz[3] = {SrcPlane(srcb + wrapz(zc - 1) * plane_b), SrcPlane(srcb + zc * plane_b),
+                                SrcPlane(srcb + wrapz(zc + 1) * plane_b)};  // index 1 + dz
         u32 o[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) o[q] = o_held[q];
@@ -311,7 +316,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         };
         C Fx, Fy, Fz;
         sc_force<C>(W(s0, ly + 1, lx + 1), G, P, Fx, Fy, Fz);
-        const Plane pd(dstb + zc * plane_b);
+        const DstPlane pd(dstb + zc * plane_b);
         if constexpr (MR) {
             T out[Q];
             // random words of this node and step (node index as in the canonical layout)
