@@ -40,11 +40,15 @@ namespace lbm {
 // and vector offsets, so an access needs no vector address arithmetic.  No
 // range limit is set (every offset the step forms lies inside the plane);
 // the last resource word is the raw-buffer format of the gfx9 family (32-bit
-// data format, no swizzle, no per-lane index).  Measured on MI355X with the
-// step on 256 x 256 x 1024: buffer access makes FP64 8% faster, but FP32,
-// FP16S and F16M 2-5% slower, although it removes 55-60 vector instructions
-// per node; so FP64 uses it, and the other kinds only for the loads of the
-// batched launch.
+// data format, no swizzle, no per-lane index).
+//
+// The step loads through buffer resources and stores through global
+// instructions, except FP64, which stores through buffers too.  Measured on
+// MI355X on 256 x 256 x 1024 (one GPU call per comparison): buffer stores
+// made FP32, FP16S and F16M 3-5% slower and FP64 faster; buffer loads were
+// 2-5% slower for those kinds in the plain march but are the faster choice
+// in the prefetching one (with 64-bit addresses its registers spill) and in
+// the batched launch.
 template <bool BUF>
 struct PlaneRef;
 
@@ -210,12 +214,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // march; they keep the three row and three column offsets instead and
     // form the nine byte offsets at each gather (one add and shift each).
     using u32 = uint32_t;
-    // Loads of the batched launch (PRIO false) go through buffer resources
-    // too: measured 2% faster there for FP32, while single grids are faster
-    // with global loads.
-    using SrcPlane = PlaneRef<ST == kF64 || !PRIO>;
-    using DstPlane = PlaneRef<ST == kF64>;
     constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M);
+    // The prefetching march (below) for the single-grid BGK launches of all
+    // but FP64: FP64 values and the MRT collision leave too few registers
+    // for it at 1024 threads, and the batched launch measured 2% slower.
+    constexpr bool kPrefetch = ST != kF64 && PRIO && !MRT;
+    using SrcPlane = PlaneRef<true>;
+    using DstPlane = PlaneRef<ST == kF64>;
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
         int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
         if constexpr (!kHoldOffsets)  // opaque copies: formed here, not hoisted
@@ -236,22 +241,22 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     const char *const srcb = static_cast<const char *>(A.src);
     char *const dstb = static_cast<char *>(A.dst);
 
-    auto gather = [&](int zc, const u32(&o_held)[9], const int(&XX)[3], const int(&YY)[3], u32 orest, C(&f)[Q]) -> C {
+    // The 19 loads of a node's pull (raw storage values; with kMassRest the
+    // FP32 rest population in `rest`), all issued before any use: the
+    // scheduler would otherwise interleave load, wait and convert for 16-bit
+    // storage.  With PRIO the wave issues them at raised priority, ahead of
+    // other waves' collision arithmetic.  Measured on MI355X: single grids
+    // FP16S 1-2% and narrow FP32 grids up to 7% faster, wide FP32 and FP64
+    // unchanged; the batched launch, whose workgroups belong to many small
+    // grids, 3-5% slower, so it keeps the default priority.
+    auto issue = [&](int zc, const u32(&o_held)[9], const int(&XX)[3], const int(&YY)[3], u32 orest, T(&raw)[Q],
+                     float &rest) {
         const SrcPlane pz[3] = {SrcPlane(srcb + wrapz(zc - 1) * plane_b), SrcPlane(srcb + zc * plane_b),
                                 SrcPlane(srcb + wrapz(zc + 1) * plane_b)};  // index 1 + dz
         u32 o[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) o[q] = o_held[q];
         if constexpr (!kHoldOffsets) offsets9(XX, YY, o);
-        // All 19 loads are issued before the first use: the scheduler would
-        // otherwise interleave load, wait and convert for 16-bit storage.
-        // With PRIO the wave issues them at raised priority, ahead of other
-        // waves' collision arithmetic.  Measured on MI355X: single grids
-        // FP16S 1-2% and narrow FP32 grids up to 7% faster, wide FP32 and
-        // FP64 unchanged; the batched launch, whose workgroups belong to
-        // many small grids, 3-5% slower, so it keeps the default priority.
-        T raw[Q];
-        float rest = 0.0f;
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -262,12 +267,24 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
+    };
+    auto decode = [&](const T(&raw)[Q], float rest, C(&f)[Q]) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) f[a] = (MR && a == 0) ? C(rest) : Tr::decode(raw[a], shift[a]);
+    };
+    // mass sum of decoded populations, or with kMassRest of the stored values
+    auto mass_of = [&](const T(&raw)[Q], float rest, const C(&f)[Q]) -> C {
         if constexpr (MR)
             return moving_sum16(raw) + rest;
         else
             return density(f);
+    };
+    auto gather = [&](int zc, const u32(&o_held)[9], const int(&XX)[3], const int(&YY)[3], u32 orest, C(&f)[Q]) -> C {
+        T raw[Q];
+        float rest = 0.0f;
+        issue(zc, o_held, XX, YY, orest, raw, rest);
+        decode(raw, rest, f);
+        return mass_of(raw, rest, f);
     };
     // psi of the node at window cell (yy, xx) into slot s, and into the ghost
     // cells that hold the same node when the tile spans whole rows or the
@@ -338,19 +355,67 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         }
     };
 
-    // Two register sets take turns as the plane being collided and the plane
-    // ahead: the march is unrolled by two, so nothing is copied between them.
-    C fa[Q], fb[Q], da = C(0), db = C(0);
-    load_plane(wrapz(zfirst - dir), 3, fb, db);
-    load_plane(zfirst, 0, fa, da);
-    auto advance = [&](int k, C(&cur)[Q], C dcur, C(&nxt)[Q], C &dnxt) {
-        load_plane(wrapz(zfirst + dir * (k + 1)), (k + 1) & 3, nxt, dnxt);
-        __syncthreads();
-        if (active) collide_store(k, cur, dcur);
-    };
-    for (int k = 0; k < kend; k += 2) {
-        advance(k, fa, da, fb, db);
-        if (k + 1 < kend) advance(k + 1, fb, db, fa, da);
+    if constexpr (!kPrefetch) {
+        // Two register sets take turns as the plane being collided and the
+        // plane ahead: the march is unrolled by two, so nothing is copied
+        // between them.
+        C fa[Q], fb[Q], da = C(0), db = C(0);
+        load_plane(wrapz(zfirst - dir), 3, fb, db);
+        load_plane(zfirst, 0, fa, da);
+        auto advance = [&](int k, C(&cur)[Q], C dcur, C(&nxt)[Q], C &dnxt) {
+            load_plane(wrapz(zfirst + dir * (k + 1)), (k + 1) & 3, nxt, dnxt);
+            __syncthreads();
+            if (active) collide_store(k, cur, dcur);
+        };
+        for (int k = 0; k < kend; k += 2) {
+            advance(k, fa, da, fb, db);
+            if (k + 1 < kend) advance(k + 1, fb, db, fa, da);
+        }
+    } else {
+        // Prefetching march: the tile's loads for plane k + 2 are issued
+        // right after the barrier of plane k, once plane k's values are
+        // decoded, and fly during plane k's collision and stores; plane
+        // k + 1's values (issued one plane earlier) only need their mass sum
+        // for psi before the barrier.  The tile keeps its planes as stored
+        // values (two sets, taking turns) and decodes at the collision.
+        T ra[Q], rb[Q];
+        float sa = 0.0f, sb = 0.0f;
+        C da = C(0), db = C(0);
+        {
+            C f[Q], d = C(0);
+            load_plane(wrapz(zfirst - dir), 3, f, d);  // psi only
+        }
+        auto tile_psi = [&](int s, const T(&raw)[Q], float rest, C &d) {
+            C f[Q];
+            if constexpr (!MR) decode(raw, rest, f);
+            d = mass_of(raw, rest, f);
+            put(s, ly + 1, lx + 1, pseudo_potential(density_of(d), rho0, inv_rho0));
+        };
+        auto ring_psi = [&](int zc, int s) {
+            C g[Q];  // only the mass sum is used
+            const C dr = gather(zc, OR, RX, RY, ORR, g);
+            put(s, ry + 1, rx + 1, pseudo_potential(density_of(dr), rho0, inv_rho0));
+        };
+        if (inside) {
+            issue(zfirst, OT, X, Y, OTR, ra, sa);
+            tile_psi(0, ra, sa, da);
+        }
+        if (ring) ring_psi(zfirst, 0);
+        if (inside) issue(wrapz(zfirst + dir), OT, X, Y, OTR, rb, sb);
+        // plane k collided from (rc, scur, dcur); plane k + 1 in (rn, sn)
+        auto advance = [&](int k, T(&rc)[Q], float &scur, C dcur, T(&rn)[Q], float sn, C &dn) {
+            if (ring) ring_psi(wrapz(zfirst + dir * (k + 1)), (k + 1) & 3);
+            if (inside) tile_psi((k + 1) & 3, rn, sn, dn);
+            __syncthreads();
+            C f[Q];
+            decode(rc, scur, f);
+            if (inside && k + 1 < kend) issue(wrapz(zfirst + dir * (k + 2)), OT, X, Y, OTR, rc, scur);
+            if (active) collide_store(k, f, dcur);
+        };
+        for (int k = 0; k < kend; k += 2) {
+            advance(k, ra, sa, da, rb, sb, db);
+            if (k + 1 < kend) advance(k + 1, rb, sb, db, ra, sa, da);
+        }
     }
 }
 
