@@ -215,10 +215,11 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // form the nine byte offsets at each gather (one add and shift each).
     using u32 = uint32_t;
     constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M);
-    // The prefetching march (below) for the single-grid BGK launches of all
-    // but FP64: FP64 values and the MRT collision leave too few registers
-    // for it at 1024 threads, and the batched launch measured 2% slower.
-    constexpr bool kPrefetch = ST != kF64 && PRIO && !MRT;
+    // The prefetching march (below) for the single-grid BGK launches, FP64
+    // only with at most 512 threads per workgroup: FP64 values at 1024
+    // threads and the MRT collision leave too few registers for it, and the
+    // batched launch measured 2% slower with it.
+    constexpr bool kPrefetch = PRIO && !MRT && (ST != kF64 || (TXS ? TXS * TYS : TYS) <= 512);
     using SrcPlane = PlaneRef<true>;
     using DstPlane = PlaneRef<ST == kF64>;
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
