@@ -42,13 +42,13 @@ namespace lbm {
 // the last resource word is the raw-buffer format of the gfx9 family (32-bit
 // data format, no swizzle, no per-lane index).
 //
-// The step loads through buffer resources and stores through global
-// instructions, except FP64, which stores through buffers too.  Measured on
-// MI355X on 256 x 256 x 1024 (one GPU call per comparison): buffer stores
-// made FP32, FP16S and F16M 3-5% slower and FP64 faster; buffer loads were
-// 2-5% slower for those kinds in the plain march but are the faster choice
-// in the prefetching one (with 64-bit addresses its registers spill) and in
-// the batched launch.
+// Stores go through global instructions except for FP64; loads go through
+// buffer resources except in the plain march of the single-grid launches
+// of the other kinds (MRT).  Measured on MI355X on 256 x 256 x 1024 (one
+// GPU call per comparison): buffer stores made FP32, FP16S and F16M 3-5%
+// slower and FP64 faster; buffer loads were 2-5% slower for those kinds in
+// the plain march but are the faster choice in the prefetching one (with
+// 64-bit addresses its registers spill) and in the batched launch.
 template <bool BUF>
 struct PlaneRef;
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // threads and the MRT collision leave too few registers for it, and the
     // batched launch measured 2% slower with it.
     constexpr bool kPrefetch = PRIO && !MRT && (ST != kF64 || (TXS ? TXS * TYS : TYS) <= 512);
-    using SrcPlane = PlaneRef<true>;
+    using SrcPlane = PlaneRef<ST == kF64 || !PRIO || kPrefetch>;
     using DstPlane = PlaneRef<ST == kF64>;
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
         int yy[3] = {YY[0], YY[1], YY[2]}, xx[3] = {XX[0], XX[1], XX[2]};
