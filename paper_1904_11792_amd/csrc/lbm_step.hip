@@ -25,6 +25,7 @@
 // FETCH_SIZE, FP32 on 256 x 256 x 1024: 80 B per node read from HBM against
 // the 76 B of algorithmic reads).
 #include <algorithm>
+#include <atomic>
 
 #include "lbm_internal.h"
 
@@ -104,8 +105,9 @@ __host__ __device__ constexpr int dyn_window(int threads) { return threads == 51
 __host__ __device__ constexpr int dyn_width_cap(int threads) { return threads == 512 ? 128 : 256; }
 
 // PRIO: gathers issued at raised wave priority (single-lattice launches).
+// PF: the prefetching march allowed (where the kind and tile have it).
 // tstep: the step number (keys the stochastic rounding of the FP32-rest kinds).
-template <int ST, int TXS, int TYS, bool MRT, bool PRIO>
+template <int ST, int TXS, int TYS, bool MRT, bool PRIO, bool PF>
 __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int tile_y, int chunk, uint32_t tstep) {
     using Tr = Storage<ST>;
     using T = typename Tr::T;
@@ -219,7 +221,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // only with at most 512 threads per workgroup: FP64 values at 1024
     // threads and the MRT collision leave too few registers for it, and the
     // batched launch measured 2% slower with it.
-    constexpr bool kPrefetch = PRIO && !MRT && (ST != kF64 || (TXS ? TXS * TYS : TYS) <= 512);
+    constexpr bool kPrefetch = PF && PRIO && !MRT && (ST != kF64 || (TXS ? TXS * TYS : TYS) <= 512);
     using SrcPlane = PlaneRef<ST == kF64 || !PRIO || kPrefetch>;
     using DstPlane = PlaneRef<ST == kF64>;
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
@@ -420,19 +422,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     }
 }
 
-template <int ST, int TX, int TY, bool MRT>
+template <int ST, int TX, int TY, bool MRT, bool PF = true>
 __device__ __forceinline__ void step_grid(const StepArgs &A) {
     const int lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ntile = A.tiles_x * A.tiles_y;
     const int tile = lb % ntile, chunk = lb / ntile;
     uint32_t tstep = 0;
     if constexpr (Storage<ST>::kMassRest) tstep = *A.step_base + A.step_add;
-    step_tile<ST, TX, TY, MRT, true>(A, tile % A.tiles_x, tile / A.tiles_x, chunk, tstep);
+    step_tile<ST, TX, TY, MRT, true, PF>(A, tile % A.tiles_x, tile / A.tiles_x, chunk, tstep);
 }
 
 template <int ST, int TX, int TY>
 __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_bgk(StepArgs A) {
     step_grid<ST, TX, TY, false>(A);
+}
+
+// The plain march (no prefetch), for grids whose planes hold more tiles than
+// the device keeps resident (launch_step).
+template <int ST, int TX, int TY>
+__global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_bgk_plain(StepArgs A) {
+    step_grid<ST, TX, TY, false, false>(A);
 }
 
 template <int ST, int TX, int TY>
@@ -459,7 +468,7 @@ __global__ __launch_bounds__(TX ? TX * TY : TY) void k_step_batch(const BatchCas
     A.dst = bc.lat[parity ^ 1];
     uint32_t tstep = 0;
     if constexpr (Storage<ST>::kMassRest) tstep = *step_base + step_add;
-    step_tile<ST, TX, TY, false, false>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z, tstep);
+    step_tile<ST, TX, TY, false, false, false>(A, it.y % A.tiles_x, it.y / A.tiles_x, it.z, tstep);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,7 +478,8 @@ struct TileEntry {
     int tx, ty;
     const void *fn[kNumStorage];
     const void *batch_fn[kNumStorage];
-    const void *mrt_fn[kNumStorage];  // MRT collision: run-time tiles, storages 0-3 only
+    const void *mrt_fn[kNumStorage];    // MRT collision: run-time tiles, storages 0-3 only
+    const void *plain_fn[kNumStorage];  // the plain march: run-time tiles
 };
 
 // Every tile has the four storage kinds of the first round of kernels; the
@@ -480,6 +490,7 @@ struct TileEntry {
 #define LBM_TILE(TXV, TYV)                                                                          \
     {TXV, TYV, {LBM_TILE_FNS4(k_step_bgk, TXV, TYV), nullptr, nullptr},                             \
      {LBM_TILE_FNS4(k_step_batch, TXV, TYV), nullptr, nullptr},                                     \
+     {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},                                        \
      {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}}
 #define LBM_TILE_RT(TXV, TYV)                                                                       \
     {TXV, TYV,                                                                                      \
@@ -487,7 +498,9 @@ struct TileEntry {
       (const void *)k_step_bgk<kBF16M, TXV, TYV>},                                                  \
      {LBM_TILE_FNS4(k_step_batch, TXV, TYV), (const void *)k_step_batch<kF16M, TXV, TYV>,          \
       (const void *)k_step_batch<kBF16M, TXV, TYV>},                                                \
-     {LBM_TILE_FNS4(k_step_mrt, TXV, TYV), nullptr, nullptr}}
+     {LBM_TILE_FNS4(k_step_mrt, TXV, TYV), nullptr, nullptr},                                       \
+     {LBM_TILE_FNS4(k_step_bgk_plain, TXV, TYV), (const void *)k_step_bgk_plain<kF16M, TXV, TYV>,  \
+      (const void *)k_step_bgk_plain<kBF16M, TXV, TYV>}}
 
 // Entries (0, 512) and (0, 1024) are the run-time shaped tiles.
 static const TileEntry kTiles[] = {
@@ -544,10 +557,37 @@ int launch_slots(int tile_index, int storage) {
     return cus * per_cu;
 }
 
+// Workgroups of the (prefetching) step kernel resident at once on the current
+// device, cached per device, tile and storage kind.
+static int resident_slots(int tile_index, int storage) {
+    constexpr int kMaxDev = 64, kMaxTiles = 16;
+    static std::atomic<int> cache[kMaxDev][kMaxTiles][kNumStorage];  // 0: not yet known
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev || tile_index >= kMaxTiles)
+        return launch_slots(tile_index, storage);
+    int v = cache[dev][tile_index][storage].load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = launch_slots(tile_index, storage);
+        if (v > 0) cache[dev][tile_index][storage].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream_t s) {
     const TileEntry &e = kTiles[tile_index];
     const void *fn = A.mrt.on ? e.mrt_fn[storage] : e.fn[storage];
     if (!fn) return hipErrorInvalidDeviceFunction;
+    // The prefetching march holds a third plane per workgroup in flight.
+    // When a plane has more tiles than the device keeps resident, the
+    // workgroups that share ring rows are not all resident together and the
+    // larger footprint evicts those rows from L2 before the neighbour reads
+    // them: FP32 on 1024 x 1024 x 1024 read 96 instead of 81 B per node from
+    // HBM and ran 5.6% slower (rocprofv3 FETCH_SIZE, MI355X).  Such grids take
+    // the plain march (measured on MI355X, FP32: prefetch faster up to 256
+    // tiles of 1024 threads per plane -- 256x256, 512x512, 1024x256 -- and
+    // slower from 512 tiles -- 1024x512, 768x768, 1024x1024).
+    if (!A.mrt.on && e.plain_fn[storage] && int64_t(A.tiles_x) * A.tiles_y > resident_slots(tile_index, storage))
+        fn = e.plain_fn[storage];
     const int nblk = A.tiles_x * A.tiles_y * A.nchunks;
     StepArgs args = A;
     void *kargs[] = {&args};

@@ -111,6 +111,33 @@ def test_launch_shapes_agree_bitwise(lbm, storage):
                 assert np.array_equal(got, ref), (tx, ty, zc)
 
 
+def test_plain_march_on_wide_planes(lbm, oracle_mod):
+    """A grid whose planes hold more tiles than the device keeps resident
+    (520 tiles of 1024 threads, 1040 of 512) takes the plain march: FP64
+    against the oracle, and FP32 and FP16S bitwise equal to the compiled
+    256 x 4 tile, which always prefetches."""
+    nx, ny, nz = 512, 1040, 3
+    spec = dict(R0=60.0, amp_rel=0.1, wavelength=3.0, noise_amp=1e-3, seed=5, rho_l=RHO_L, rho_v=RHO_V)
+    f0 = oracle_mod.init_ligament(nx, ny, nz, **spec)
+    ref = oracle_mod.run(f0, 3, 0.9, -5.5)
+    lat = lbm.Lattice(nx, ny, nz, 0.9, -5.5, storage="f64")
+    lat.set_launch(0, 512, 3)
+    lat.init_ligament(**spec)
+    lat.step(3)
+    assert _relerr(lat.populations().cpu().numpy(), ref) < 1e-13
+    lat.close()
+    for storage in ("f32", "f16s"):
+        out = []
+        for launch in ((0, 1024, 3), (256, 4, 3)):
+            lat = lbm.Lattice(nx, ny, nz, 0.9, -5.5, storage=storage, rho_ref=RHO_V)
+            lat.set_launch(*launch)
+            lat.init_ligament(**spec)
+            lat.step(3)
+            out.append(lat.populations().cpu().numpy())
+            lat.close()
+        assert np.array_equal(out[0], out[1]), storage
+
+
 def test_fp64_generic_state_via_import(lbm, oracle_mod):
     f = workloads.random_populations((9, 10, 11), seed=4, base=1.3, spread=0.5)
     lat = lbm.Lattice(11, 10, 9, 0.7, -5.0, storage="f64")
