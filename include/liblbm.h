@@ -349,7 +349,11 @@ int lbm_set_step(lbm_ctx *ctx, int64_t step);
  * workgroup per compute unit) and 18 planes charge a round's start-up, the
  * two extra psi planes of each chunk and the tail; smaller grids, which live
  * in the caches, take the chunk that gives about 256 workgroups (down to one
- * plane).
+ * plane).  The shape does not change the results (bit for bit); neither does
+ * the kernel's choice, per launch, between marching with the tile's loads
+ * for plane z + 2 in flight during plane z's collision and the plain march
+ * (taken by FP32 and FP64 when a plane has more tiles than the device keeps
+ * resident).
  */
 typedef struct {
     int32_t tile_x, tile_y, zchunk;

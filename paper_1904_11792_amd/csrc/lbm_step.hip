@@ -479,7 +479,7 @@ struct TileEntry {
     const void *fn[kNumStorage];
     const void *batch_fn[kNumStorage];
     const void *mrt_fn[kNumStorage];    // MRT collision: run-time tiles, storages 0-3 only
-    const void *plain_fn[kNumStorage];  // the plain march: run-time tiles
+    const void *plain_fn[kNumStorage];  // the plain march: run-time tiles, FP64 and FP32
 };
 
 // Every tile has the four storage kinds of the first round of kernels; the
@@ -499,8 +499,8 @@ struct TileEntry {
      {LBM_TILE_FNS4(k_step_batch, TXV, TYV), (const void *)k_step_batch<kF16M, TXV, TYV>,          \
       (const void *)k_step_batch<kBF16M, TXV, TYV>},                                                \
      {LBM_TILE_FNS4(k_step_mrt, TXV, TYV), nullptr, nullptr},                                       \
-     {LBM_TILE_FNS4(k_step_bgk_plain, TXV, TYV), (const void *)k_step_bgk_plain<kF16M, TXV, TYV>,  \
-      (const void *)k_step_bgk_plain<kBF16M, TXV, TYV>}}
+     {(const void *)k_step_bgk_plain<kF64, TXV, TYV>, (const void *)k_step_bgk_plain<kF32, TXV, TYV>, \
+      nullptr, nullptr, nullptr, nullptr}}
 
 // Entries (0, 512) and (0, 1024) are the run-time shaped tiles.
 static const TileEntry kTiles[] = {
@@ -585,7 +585,9 @@ hipError_t launch_step(int tile_index, int storage, const StepArgs &A, hipStream
     // HBM and ran 5.6% slower (rocprofv3 FETCH_SIZE, MI355X).  Such grids take
     // the plain march (measured on MI355X, FP32: prefetch faster up to 256
     // tiles of 1024 threads per plane -- 256x256, 512x512, 1024x256 -- and
-    // slower from 512 tiles -- 1024x512, 768x768, 1024x1024).
+    // slower from 512 tiles -- 1024x512, 768x768, 1024x1024).  The 16-bit
+    // kinds, with half the bytes per plane, keep the prefetch: 1-2% faster
+    // on 1024x512x1024, 768x768x1024 and 1024x1024x2047.
     if (!A.mrt.on && e.plain_fn[storage] && int64_t(A.tiles_x) * A.tiles_y > resident_slots(tile_index, storage))
         fn = e.plain_fn[storage];
     const int nblk = A.tiles_x * A.tiles_y * A.nchunks;

@@ -83,7 +83,7 @@ def test_fp64_every_tile_shape(lbm, oracle_mod):
             lat.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s", "f16m", "bf16m"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "f16m", "bf16m"])
 def test_launch_shapes_agree_bitwise(lbm, storage):
     """Every launch shape the storage kind has (compiled tiles, and the
     run-time tiles of 512 and 1024 threads), with z chunks of 1, 2 and 5
@@ -94,7 +94,7 @@ def test_launch_shapes_agree_bitwise(lbm, storage):
     nx, ny, nz = 75, 21, 23
     spec = dict(R0=6.0, amp_rel=0.15, wavelength=23.0, noise_amp=1e-3, seed=8, rho_l=RHO_L, rho_v=RHO_V)
     tiles = [(0, 512), (0, 1024)]
-    if storage in ("f32", "f16s", "bf16s"):
+    if storage in ("f64", "f32", "f16s", "bf16s"):
         tiles += [t for t in lbm.lbm_list_tiles() if t[0] != 0]
     ref = None
     for tx, ty in tiles:
@@ -113,9 +113,10 @@ def test_launch_shapes_agree_bitwise(lbm, storage):
 
 def test_plain_march_on_wide_planes(lbm, oracle_mod):
     """A grid whose planes hold more tiles than the device keeps resident
-    (520 tiles of 1024 threads, 1040 of 512) takes the plain march: FP64
-    against the oracle, and FP32 and FP16S bitwise equal to the compiled
-    256 x 4 tile, which always prefetches."""
+    (520 tiles of 1024 threads, 1040 of 512) takes the plain march in FP64
+    and FP32: FP64 against the oracle, FP32 bitwise equal to the compiled
+    256 x 4 tile, which always prefetches; FP16S, which keeps the prefetch on
+    such grids, bitwise equal to that tile as well."""
     nx, ny, nz = 512, 1040, 3
     spec = dict(R0=60.0, amp_rel=0.1, wavelength=3.0, noise_amp=1e-3, seed=5, rho_l=RHO_L, rho_v=RHO_V)
     f0 = oracle_mod.init_ligament(nx, ny, nz, **spec)
