@@ -16,14 +16,15 @@
 // the same time level.  Each workgroup owns a tile_x * tile_y column of the
 // grid (one thread per node) and marches it over `zchunk` planes along z.
 // Per plane it gathers the populations of its tile (kept in registers for the
-// collision one plane later) and of a one-node ring around the tile (only
-// their density is kept), and writes psi into a four-plane window in LDS; the
-// force then reads psi(z-1), psi(z), psi(z+1) from LDS.  HBM traffic stays at
-// 19 loads + 19 stores per node: the ring and the two extra planes of a z
-// chunk are re-reads of lines that neighbouring tiles, scheduled on the same
-// XCD at the same time, have mostly just brought into L2 (rocprofv3
-// FETCH_SIZE, FP32 on 256 x 256 x 1024: 80 B per node read from HBM against
-// the 76 B of algorithmic reads).
+// collision one plane later; in the prefetching march the loads go out two
+// planes ahead) and of a one-node ring around the tile (only their mass sum
+// is kept), and writes psi into a four-plane window in LDS; the force then
+// reads psi(z-1), psi(z), psi(z+1) from LDS.  HBM traffic stays near 19
+// loads + 19 stores per node: the ring and the two extra planes of a z chunk
+// are re-reads of lines that neighbouring tiles, scheduled on the same XCD
+// at the same time, have mostly just brought into L2 (rocprofv3 FETCH_SIZE,
+// FP32 on 256 x 256 x 1024: 82 B per node read from HBM against the 76 B of
+// algorithmic reads).
 #include <algorithm>
 #include <atomic>
 
