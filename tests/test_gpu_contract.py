@@ -39,6 +39,22 @@ def test_degenerate_grids_match_oracle(lbm, oracle_mod, shape):
     assert _relerr(lat.populations().cpu().numpy(), ref) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 1), (1, 3, 2), (3, 1, 5)])
+@pytest.mark.parametrize("storage,bar", [("f32", 1e-5), ("f16s", 2e-2), ("f16m", 2e-2)])
+def test_degenerate_grids_reduced_precision(lbm, oracle_mod, shape, storage, bar):
+    """The same self-wrapping grids through the 1024-thread kernels of the
+    reduced-precision kinds (the prefetching march with one- and two-plane
+    extents): density against the FP64 oracle after 25 steps."""
+    nx, ny, nz = shape
+    f = workloads.random_populations((nz, ny, nx), seed=sum(shape), base=1.1, spread=0.4)
+    lat = lbm.Lattice(nx, ny, nz, 0.8, -5.5, storage=storage, rho_ref=1.0)
+    lat.set_launch(0, 1024, nz)  # one chunk: the march wraps around the whole extent
+    lat.set_populations(f)
+    lat.step(25)
+    ref = oracle_mod.run(f, 25, 0.8, -5.5).sum(axis=0)
+    assert _relerr(lat.populations().cpu().numpy().sum(axis=0), ref) < bar
+
+
 def test_zero_steps_and_step_counter(lbm):
     f = workloads.random_populations((4, 4, 4), seed=1)
     lat = lbm.Lattice(4, 4, 4, 0.9, -5.0, storage="f32")
