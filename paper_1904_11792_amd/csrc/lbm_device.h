@@ -111,19 +111,6 @@ __host__ __device__ inline uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// Stochastic rounding of the 18 moving populations h[1..18] (FP32) to the
-// 16-bit storage type, into out[1..18], returning their FP32 sum.  A value
-// is rounded up in magnitude with probability (distance to the lower
-// neighbour) / (spacing), so the rounding error has zero mean: increments
-// smaller than the 16-bit spacing survive on average instead of being
-// rounded away step after step (round-to-nearest holds a slowly changing
-// population at the same stored value, and a slowly growing flow with it).
-// Population a takes a window of D random bits (D = the number of FP32
-// mantissa bits the 16-bit type drops: 13 for half, 16 for bfloat16) from
-// word (a - 1) / 6 at offset ((a - 1) mod 6) (32 - D) / 5 (overlapping
-// windows, each uniform), adds it to the FP32 bit pattern and truncates.
-// Below the half-precision normal range (|h| < 2^-14, a spacing of 2^-24)
-// F16M truncates toward zero.
 // FP32 sum of the 18 moving populations as stored (slots 1..18 of v), in the
 // order 1, 2, ..., 18.  The values are multiples of 2^-24 (half) or carry 8
 // significant bits (bfloat16), so the sum is exact unless their magnitudes
@@ -136,6 +123,19 @@ __device__ inline float moving_sum16(const T (&v)[Q]) {
     return s;
 }
 
+// Stochastic rounding of the 18 moving populations h[1..18] (FP32) to the
+// 16-bit storage type, into out[1..18], returning their FP32 sum (moving_sum16).  A value
+// is rounded up in magnitude with probability (distance to the lower
+// neighbour) / (spacing), so the rounding error has zero mean: increments
+// smaller than the 16-bit spacing survive on average instead of being
+// rounded away step after step (round-to-nearest holds a slowly changing
+// population at the same stored value, and a slowly growing flow with it).
+// Population a takes a window of D random bits (D = the number of FP32
+// mantissa bits the 16-bit type drops: 13 for half, 16 for bfloat16) from
+// word (a - 1) / 6 at offset ((a - 1) mod 6) (32 - D) / 5 (overlapping
+// windows, each uniform), adds it to the FP32 bit pattern and truncates.
+// Below the half-precision normal range (|h| < 2^-14, a spacing of 2^-24)
+// F16M truncates toward zero.
 template <typename Tr>
 __device__ inline float round_moving_sr(const float (&h)[Q], typename Tr::T (&out)[Q], const uint32_t (&rnd)[3]) {
     using T = typename Tr::T;
