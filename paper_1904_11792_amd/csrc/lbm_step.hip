@@ -46,7 +46,8 @@ namespace lbm {
 //
 // Stores go through global instructions except for FP64; loads go through
 // buffer resources except in the plain march of the single-grid launches
-// of the other kinds (MRT).  Measured on MI355X on 256 x 256 x 1024 (one
+// of the other kinds (MRT, and FP32 on planes with more tiles than the
+// device keeps resident).  Measured on MI355X on 256 x 256 x 1024 (one
 // GPU call per comparison): buffer stores made FP32, FP16S and F16M 3-5%
 // slower and FP64 faster; buffer loads were 2-5% slower for those kinds in
 // the plain march but are the faster choice in the prefetching one (with
@@ -145,8 +146,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
         for (int k = 0; k < 3; ++k) skey[k] = hash32(3u * tstep + uint32_t(k) + 0x9E3779B9u);
     }
     // A gather returns the node's mass sum d: the density, or with kMassRest
-    // the excess m = sum h_a (the moving populations as stored, summed in
-    // pairs, then the FP32 rest), from which density_of gives the density.
+    // the excess m = sum h_a (the moving populations as stored, in order,
+    // then the FP32 rest), from which density_of gives the density.
     // The tile's sums are kept from the gather to the collision one plane
     // later.
     auto density_of = [&](C d) -> C { return MR ? rho_ref + d : d; };
@@ -207,8 +208,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
                        row_offset(wrapi(rgy + 1, ny), rowst, rsh, nx)};
     const int RYR = MR ? row_offset(rgy, rowst / 2, rsh, nx) : 0;
 
-    // Addresses: a z plane (PlaneRef: FP64 through a buffer resource, the
-    // other kinds through a 64-bit pointer), the population segment as the
+    // Addresses: a z plane (PlaneRef: a buffer resource or a 64-bit pointer,
+    // chosen below per access kind), the population segment as the
     // wave-uniform offset and a 32-bit byte offset within the segment (the
     // host keeps a plane below 4 GiB).  The byte offsets of the nine (row,
     // column) combinations a pull reads from -- index (1 - c_y) 3 + (1 - c_x)
