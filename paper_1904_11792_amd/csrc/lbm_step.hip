@@ -214,16 +214,19 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, int tile_x, int til
     // host keeps a plane below 4 GiB).  The byte offsets of the nine (row,
     // column) combinations a pull reads from -- index (1 - c_y) 3 + (1 - c_x)
     // -- and of the FP32 rest population are fixed for the whole march.
-    // The bfloat16 kernels would spill with eighteen offsets held over the
-    // march; they keep the three row and three column offsets instead and
-    // form the nine byte offsets at each gather (one add and shift each).
     using u32 = uint32_t;
-    constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M);
     // The prefetching march (below) for the single-grid BGK launches, FP64
     // only with at most 512 threads per workgroup: FP64 values at 1024
     // threads and the MRT collision leave too few registers for it, and the
     // batched launch measured 2% slower with it.
     constexpr bool kPrefetch = PF && PRIO && !MRT && (ST != kF64 || (TXS ? TXS * TYS : TYS) <= 512);
+    // The bfloat16 kernels of the plain single-grid march (global loads)
+    // would spill with eighteen offsets held over the march; they keep the
+    // three row and three column offsets instead and form the nine byte
+    // offsets at each gather (one add and shift each).  With buffer loads
+    // they hold them (no spill; BF16S 1.8% and BF16M 1.2% faster on
+    // 256 x 256 x 1024, MI355X).
+    constexpr bool kHoldOffsets = !(ST == kBF16S || ST == kBF16M) || kPrefetch || !PRIO;
     using SrcPlane = PlaneRef<ST == kF64 || !PRIO || kPrefetch>;
     using DstPlane = PlaneRef<ST == kF64>;
     auto offsets9 = [&](const int(&XX)[3], const int(&YY)[3], u32(&o)[9]) {
