@@ -20,10 +20,13 @@ SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_capi.hip"]
 # Host-sanitized build (build(sanitize_host=True)): the host code of the
 # library instrumented with AddressSanitizer and UndefinedBehaviorSanitizer;
 # the runtime is not linked in, so a process must preload clang's shared ASan
-# runtime (which carries the UBSan handlers) to load it.
+# runtime (which carries the UBSan handlers) to load it.  It is for testing
+# the host code only: its device code is compiled without optimisation (a
+# third of the compile time), and its kernels are not meant to run.
 OUT_HOSTSAN = os.path.join(HERE, "liblbm_hostsan.so")
 OBJDIR_HOSTSAN = os.path.join(HERE, "_build_hostsan")
-HOSTSAN_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+HOSTSAN_FLAGS = ["-O1", "-Xarch_device", "-O0", "-Xarch_host", "-g",
+                 "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                  "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
