@@ -195,6 +195,33 @@ def test_dropping_frozen_cases_leaves_live_ones_bitwise(lbm):
     torch.cuda.synchronize()
 
 
+def test_batch_with_every_case_frozen(lbm):
+    """Once every case has diverged the launch list is empty: later steps, in
+    graph chunks or plain, launch nothing, raise nothing and leave each
+    frozen state as it was."""
+    import torch
+
+    cases = workloads.batch64(seed=11, count=2)
+    params = [lbm.make_params(c.nx, c.ny, c.nz, 0.5001, -7.5, storage="f32") for c in cases]
+    specs = [lbm.make_ligament(c.nx, c.ny, c.nz, R0=c.R0, amp_rel=c.amp_rel, wavelength=c.wavelength,
+                               rho_l=2.3, rho_v=0.1, seed=c.seed) for c in cases]
+    st = torch.cuda.Stream()  # graph capture needs a stream of its own
+    b = lbm.Batch(params, stream=st)
+    b.init(specs)
+    b.set_graph_chunk(100)
+    b.step(1000)  # the check at step 1000 freezes both cases on the device
+    d = b.diagnostics()  # ... and this drops them from the launch list
+    assert all(x["nonfinite"] > 0 for x in d)
+    frozen = [b.fields(i, rho=False, pop=True)["pop"].cpu().numpy() for i in range(len(cases))]
+    b.step(250)  # two graph chunks' worth and 50 plain steps over no items
+    d = b.diagnostics()
+    assert all(x["nonfinite"] > 0 for x in d)
+    for i in range(len(cases)):
+        assert np.array_equal(b.fields(i, rho=False, pop=True)["pop"].cpu().numpy(), frozen[i], equal_nan=True), i
+    b.close()
+    torch.cuda.synchronize()
+
+
 def test_diag_ring_keeps_last_records(lbm):
     lat = lbm.Lattice(8, 8, 8, 0.9, -5.0, storage="f32")
     lat.set_populations(workloads.random_populations((8, 8, 8), seed=4))
